@@ -1,0 +1,202 @@
+"""Throughput benchmark of the D3Q19 flux-inlet step on one MI355X.
+
+Default workload: 256^3 pack of overlapping solid spheres (seed 2, radii
+uniform in [6, 10], porosity 0.35, six pure-fluid reservoir layers at each z
+end), FP32 distributions, BGK tau = 0.8, adaptive flux inlet with Darcy
+velocity 1e-4 (Q* = 1e-4 * 256^2), pressure outlet rho = 1.
+
+Prints one JSON line: MLUPS over pore sites for the timed steps, the roofline
+of the fused stream-collide kernel (algorithmic bytes per launch over its
+mean HIP-event duration), and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    # name: (builder, lattice kwargs, description)
+    "pack256": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp32"),
+    "pack512": dict(n=512, porosity=0.25, seed=5, reservoir=6, tau=0.8, darcy=1e-5, precision="fp32"),
+    "slit": dict(slit=True, tau=1.0, q=0.5, precision="fp64"),
+}
+
+
+def bytes_per_lup(precision: str) -> int:
+    """Algorithmic bytes of one pore-site update: 19 populations read and
+    written once in the storage type, plus 18 int32 pull indices."""
+    elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
+    return 19 * 2 * elem + 18 * 4
+
+
+def make_workload(cfg):
+    from paper_1806_10589_amd import inputs
+
+    if cfg.get("slit"):
+        mask = inputs.slit_channel(16, 16, 64)
+        return mask, dict(tau=cfg["tau"], q_target=cfg["q"], precision=cfg["precision"],
+                          periodic_x=False, periodic_y=True), {"porosity": float((mask == 0).mean())}
+    mask, phi, nsph = inputs.sphere_pack(cfg["n"], cfg["porosity"], seed=cfg["seed"],
+                                         reservoir_layers=cfg["reservoir"])
+    q = cfg["darcy"] * mask.shape[1] * mask.shape[2]
+    return mask, dict(tau=cfg["tau"], q_target=q, precision=cfg["precision"], periodic_x=True,
+                      periodic_y=True), {"porosity": phi, "spheres": nsph}
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
+    from paper_1806_10589_amd import fluxlbm
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        fluxlbm.flbm_copy_kernel(a.data_ptr(), b.data_ptr(), nbytes, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fluxlbm.flbm_copy_kernel(a.data_ptr(), b.data_ptr(), nbytes, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(mask, kw, steps):
+    """FP64 oracle on the same workload, `steps` steps after one warm-up step."""
+    import oracle
+
+    orc = oracle.OracleLattice(mask, tau=kw["tau"], q_target=kw["q_target"], rho_out=1.0,
+                               periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
+    orc.init_equilibrium(1.0)
+    orc.step(1, record=False)
+    t0 = time.perf_counter()
+    orc.step(steps, record=False)
+    dt = time.perf_counter() - t0
+    n_pore = int((mask == 0).sum())
+    return {
+        "value": n_pore * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": oracle.oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"{steps} steps of the full {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]} lattice "
+                  f"after 1 warm-up step ({dt:.1f} s); FP64 dense push-scheme oracle, OpenMP over z",
+        "mlups_per_voxel": mask.size * steps / dt / 1e6,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="pack256", choices=sorted(CONFIGS))
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the z-slab sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1806_10589_amd import fluxlbm
+
+    cfg = CONFIGS[args.config]
+    mask, kw, info = make_workload(cfg)
+    print(f"[bench] workload {args.config}: mask {mask.shape}, pore sites {(mask == 0).sum()}",
+          file=sys.stderr, flush=True)
+    lat = fluxlbm.Lattice(mask, watchdog_every=1000, **kw)
+    lat.init_equilibrium(1.0)
+    n = lat.n_sites
+
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    if lat.sync() != fluxlbm.FLBM_OK:
+        raise SystemExit("unstable during warm-up")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(lat.stream)
+    lat.step(args.steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    status = lat.sync()
+    ms_step = ms_total / args.steps
+    mlups = n * args.steps / (ms_total * 1e-3) / 1e6
+    q_in, q_out, rho_in, _ = lat.boundary()
+    print(f"[bench] {args.steps} steps in {ms_total:.1f} ms (wall {wall:.2f} s): {mlups:.1f} MLUPS, "
+          f"Q_in {q_in:.6f} Q_out {q_out:.6f} rho_in {rho_in:.6f}", file=sys.stderr, flush=True)
+
+    # per-kernel durations with HIP events on the launch stream
+    ms_plane, ms_kernel = lat.profile_kernels(args.profile_steps)
+    bpl = bytes_per_lup(kw["precision"])
+    achieved = n * bpl / (ms_kernel * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "kernel": "k_stream_collide",
+        "kernel_ms": round(ms_kernel, 5),
+        "plane_kernel_ms": round(ms_plane, 5),
+        "bytes_per_lup": bpl,
+    }
+    out = {
+        "metric": "MLUPS (pore sites) + HBM GB/s; steps-to-flux-tol, learned vs plain",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16dev": "f16-storage/f32"}[kw["precision"]],
+        "data": "synthetic",
+        "config": {
+            "workload": args.config,
+            "mask": list(mask.shape),
+            "pore_sites": n,
+            "inlet_sites": lat.a_in,
+            "tau": kw["tau"],
+            "q_target": kw["q_target"],
+            "precision": kw["precision"],
+            **info,
+        },
+        "hbm_gbs_model": round(mlups * bpl / 1e3, 1),
+        "status": "ok" if status == fluxlbm.FLBM_OK else "unstable",
+        "roofline": roofline,
+    }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_copy:
+        out["copy_gbs"] = round(copy_bandwidth(torch), 1)
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        out["cpu_baseline"] = cpu_baseline(mask, kw, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * fluxlbm.h -- C ABI of the MI355X (gfx950) D3Q19 lattice-Boltzmann library
+ * with the adaptive volumetric-flux inlet of McClure, Li, Sheppard and
+ * Miller, "An Adaptive Volumetric Flux Boundary Condition for Lattice
+ * Boltzmann Methods" (arXiv:1806.10589).
+ *
+ * What one time step computes (flbm_step):
+ *   - pull streaming of the D3Q19 populations over a sparse list of pore
+ *     sites (Methods, eq. LBE), with halfway bounce-back at solid voxels and
+ *     at non-periodic side faces;
+ *   - at the inlet plane z = 0: the uniform inlet density that makes the
+ *     total volumetric flux equal the target, found by integrating the
+ *     consistency condition over the inlet pore sites (Methods, eq. inlet,
+ *     eq. flux, eq. potential), then the pressure condition with that
+ *     density, closed with Hecht and Harting's transverse corrections
+ *     (Appendix B);
+ *   - at the outlet plane z = nz-1: the same pressure condition with a fixed
+ *     density (Methods, last paragraph);
+ *   - collision at every pore site: BGK (single fluid) or the colour-gradient
+ *     two-fluid model of Appendix A;
+ *   - per-step FP64 records of rho_in, Q_in, Q_out; total mass and max |u|
+ *     at watchdog points.
+ *
+ * Conventions
+ *   - Lattice units throughout. Masks are uint8 [nz][ny][nx], x fastest
+ *     (flat index x + nx*(y + ny*z)), nonzero = solid. Flow is along +z.
+ *   - Sites are the pore voxels in raster order (z slowest, x fastest), so
+ *     the inlet sites are [0, a_in) and the outlet sites [n - a_out, n).
+ *   - Host buffers are owned by the caller and only read or written during
+ *     the call. Device memory is either caller-owned (flbm_bind_device_memory)
+ *     or allocated by the library on first use and freed by flbm_destroy.
+ *   - All device work is enqueued on the stream given to flbm_create (a
+ *     hipStream_t; NULL means the null stream). Calls that return host data
+ *     synchronise that stream.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Every call returns FLBM_OK (0) or a negative flbm_status; the text of
+ *     the last error of a context is available from flbm_last_error.
+ */
+#ifndef FLUXLBM_H
+#define FLUXLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t flbm_status;
+
+#define FLBM_OK 0
+#define FLBM_EINVAL (-1)    /* bad argument or parameter */
+#define FLBM_ENOINLET (-2)  /* no pore site on the inlet plane: eq. potential divides by A = 0 */
+#define FLBM_ENOMEM (-3)    /* host or device allocation failed */
+#define FLBM_EHIP (-4)      /* HIP runtime error; text in flbm_last_error */
+#define FLBM_EUNSTABLE (-5) /* watchdog saw a non-finite value or max|u| above the limit */
+#define FLBM_EINDEX (-6)    /* 19 * padded sites does not fit a signed 32-bit index */
+#define FLBM_EBOUND (-7)    /* caller's device buffer is smaller than flbm_device_bytes */
+#define FLBM_ESTATE (-8)    /* call not valid in the context's current state */
+
+/* Storage precision of the distributions. Boundary sums and the inlet
+ * density are FP64 in every mode. */
+#define FLBM_FP64 0
+#define FLBM_FP32 1
+#define FLBM_FP16DEV 2 /* FP16 storage of scaled deviations f - w_q, FP32 arithmetic */
+
+/* Collision model. */
+#define FLBM_BGK 0
+#define FLBM_COLOUR 1 /* two-fluid colour-gradient model (Appendix A) */
+
+/* Treatment of the z faces. FLBM_Z_FLUX is the paper's set-up: flux inlet at
+ * z = 0, pressure outlet at z = nz-1 (Methods, last paragraph). The other two
+ * close the box (periodic, or bounce-back walls beyond both z faces). */
+#define FLBM_Z_FLUX 0
+#define FLBM_Z_PERIODIC 1
+#define FLBM_Z_WALL 2
+
+typedef struct flbm_params {
+    int32_t nx, ny, nz;         /* mask dimensions; nz >= 3 */
+    int32_t periodic_x;         /* 1: periodic in x; 0: bounce-back walls beyond x faces */
+    int32_t periodic_y;         /* same for y */
+    int32_t z_mode;             /* FLBM_Z_* */
+    int32_t reservoir_layers;   /* z-planes forced to fluid at each end (pure-fluid reservoirs) */
+    int32_t precision;          /* FLBM_FP64 / FLBM_FP32 / FLBM_FP16DEV */
+    int32_t model;              /* FLBM_BGK / FLBM_COLOUR */
+    int32_t watchdog_every;     /* mass, max|u| and finiteness checked at least this often (steps) */
+    double tau;                 /* relaxation time, > 1/2; nu = (tau - 1/2)/3 */
+    double rho0;                /* reference density of the incompressible model (eq. m357) */
+    double q_target;            /* target volumetric flux Q* through z = 0, lu^3/lt */
+    double rho_out;             /* outlet density; pressure p = rho/3 (eq. pressure) */
+    double alpha;               /* colour model: interfacial-stress strength (Appendix A) */
+    double beta;                /* colour model: recolouring strength (Appendix A) */
+    double phi_solid;           /* colour model: phase value seen at solid neighbours */
+    double umax_limit;          /* watchdog threshold on |u| (the paper's rule of thumb: 0.1) */
+} flbm_params;
+
+typedef struct flbm_ctx flbm_ctx;
+
+/* Fill *p with defaults: periodic x and y, FLBM_Z_FLUX, FP32, BGK, tau 0.8,
+ * rho0 1, q_target 0, rho_out 1, watchdog every 1000 steps, umax_limit 0.1,
+ * alpha 0.005, beta 0.7, phi_solid 0. Dimensions are set to zero. */
+flbm_status flbm_default_params(flbm_params *p);
+
+/* Build the sparse pore lattice from a host solid mask (uint8 [nz][ny][nx],
+ * nonzero = solid; copied, not kept) and create a context whose device work
+ * goes to `hip_stream` (hipStream_t or NULL). No device memory is touched
+ * until flbm_bind_device_memory or the first call that needs it.
+ * Errors: FLBM_EINVAL (null pointer, dims, tau <= 1/2, rho0 <= 0, unknown
+ * mode), FLBM_ENOINLET (FLBM_Z_FLUX with no pore site at z = 0),
+ * FLBM_EINDEX (lattice too large for 32-bit indices), FLBM_ENOMEM. */
+flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *hip_stream,
+                        flbm_ctx **out);
+
+/* Release the context and, if the library allocated it, its device memory. */
+flbm_status flbm_destroy(flbm_ctx *c);
+
+/* Device bytes the context needs (distributions in two copies, the int32
+ * pull table, FP64 reduction scratch and history). */
+flbm_status flbm_device_bytes(const flbm_ctx *c, size_t *bytes);
+
+/* Use caller-owned device memory (e.g. a torch uint8 tensor) of at least
+ * flbm_device_bytes bytes, 256-byte aligned; it must outlive the context.
+ * Only valid before any device memory is in use (else FLBM_ESTATE).
+ * Uploads the pull table and sets the rest state rho = rho_out, u = 0.
+ * Errors: FLBM_EBOUND if too small, FLBM_EINVAL if null or misaligned. */
+flbm_status flbm_bind_device_memory(flbm_ctx *c, void *dev_ptr, size_t bytes);
+
+/* Counts: pore sites, inlet pore sites (the area A of eq. potential), outlet
+ * pore sites. */
+flbm_status flbm_num_sites(const flbm_ctx *c, int64_t *n_sites, int64_t *a_in, int64_t *a_out);
+
+/* Site coordinates, host int32 [n_sites][3] = (x, y, z), in site order. */
+flbm_status flbm_get_site_coords(const flbm_ctx *c, int32_t *xyz);
+
+/* Set every pore site to the equilibrium with density rho and velocity u
+ * (App. B equilibrium), reset the step counter, history and watchdog flag. */
+flbm_status flbm_init_equilibrium(flbm_ctx *c, double rho, double ux, double uy, double uz);
+
+/* Target flux Q* (eq. flux) used from the next step on. */
+flbm_status flbm_set_target_flux(flbm_ctx *c, double q_target);
+
+/* Outlet density used from the next step on. */
+flbm_status flbm_set_outlet_density(flbm_ctx *c, double rho_out);
+
+/* Enqueue n time steps on the context's stream (asynchronous). */
+flbm_status flbm_step(flbm_ctx *c, int32_t n);
+
+/* Wait for the context's stream. Returns FLBM_EUNSTABLE if a watchdog check
+ * since the last init/write found a non-finite value or |u| > umax_limit. */
+flbm_status flbm_sync(flbm_ctx *c);
+
+/* Boundary values of the last completed step (synchronises): Q_in (sum of
+ * u_z over the inlet sites after the pressure condition; equals Q* up to
+ * rounding), Q_out (the same sum over the outlet sites), rho_in (eq.
+ * potential), rho_out. Any pointer may be NULL. */
+flbm_status flbm_get_boundary(flbm_ctx *c, double *q_in, double *q_out, double *rho_in,
+                              double *rho_out);
+
+/* Per-step FP64 history of the last n steps, oldest first, 5 doubles per
+ * step: rho_in, Q_in, Q_out, total mass, max|u|. Mass and max|u| are NaN on
+ * steps that were not watchdog points. n must not exceed the number of steps
+ * taken nor the ring capacity (flbm_history_capacity). Synchronises. */
+flbm_status flbm_get_history(flbm_ctx *c, double *buf, int32_t n);
+flbm_status flbm_history_capacity(const flbm_ctx *c, int32_t *cap);
+
+/* Number of steps taken since the last init/write. */
+flbm_status flbm_step_count(const flbm_ctx *c, int64_t *steps);
+
+/* Density and velocity of every pore site (host FP64 arrays of n_sites,
+ * site order), from the stored post-collision state; collision conserves
+ * them, so they are the post-boundary moments of the last step. Any pointer
+ * may be NULL. Synchronises. */
+flbm_status flbm_read_fields(flbm_ctx *c, double *rho, double *ux, double *uy, double *uz);
+
+/* Read / write the stored distributions as host FP64 [19][n_sites] (q
+ * slowest, site order; absolute values f_q, not deviations). Writing
+ * converts to the storage precision, resets the step counter, history and
+ * watchdog flag. Synchronise. */
+flbm_status flbm_read_distributions(flbm_ctx *c, double *f);
+flbm_status flbm_write_distributions(flbm_ctx *c, const double *f);
+
+/* Host copy of the pull table, int32 [18][n_sites] (row q-1 for direction
+ * q = 1..18): the flat index into a [19][n_pad] distribution array that
+ * streams into (q, site) -- q*n_pad + source site, opp(q)*n_pad + site for
+ * halfway bounce-back, or 19*n_pad for a boundary unknown (the unknowns of
+ * Methods, before eq. inlet). Host-only; needs no device. */
+flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
+
+/* Raw checkpoint of the stored state: flbm_state_bytes gives the size; save
+ * copies the current distribution buffer (storage precision, deviations)
+ * and the step count to host memory; load restores it, so that a resumed run
+ * is bitwise identical to an uninterrupted one. Synchronise. */
+flbm_status flbm_state_bytes(const flbm_ctx *c, size_t *bytes);
+flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes);
+flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes);
+
+/* Testing aid: enabled = 0 turns collision off (relaxation rate 0), so a
+ * step is pure streaming plus boundary conditions. */
+flbm_status flbm_debug_set_collision(flbm_ctx *c, int32_t enabled);
+
+/* Total mass, max |u| and a non-finite flag of the current state, computed
+ * on the device from the stored distributions (synchronises). */
+flbm_status flbm_get_observables(flbm_ctx *c, double *mass, double *umax, int32_t *nonfinite);
+
+/* Device pointers of the current distribution buffer (layout [19][n_pad] of
+ * the storage type, deviations f - w_q) and of the pull table (int32
+ * [18][n_pad]); for profiling and zero-copy inspection. */
+flbm_status flbm_device_layout(const flbm_ctx *c, void **f_cur, void **nbr, int64_t *n_pad);
+
+/* Profiling: run n steps launched one by one (no graph, no watchdog
+ * reduction), each kernel bracketed by HIP events on the context's stream,
+ * and return the mean duration in milliseconds of the inlet-plane reduction
+ * and of the fused stream-collide kernel. The steps are real steps (the
+ * state advances). Synchronises. */
+flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, double *ms_step);
+
+/* Stream-copy calibration kernel: copies `bytes` (a multiple of 16, both
+ * pointers 16-byte aligned) from src to dst on `hip_stream`, 16 bytes per
+ * lane with non-temporal stores. For measuring attainable HBM bandwidth
+ * beside the step. */
+flbm_status flbm_copy_kernel(const void *src, void *dst, size_t bytes, void *hip_stream);
+
+const char *flbm_status_string(flbm_status s);
+const char *flbm_last_error(const flbm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLUXLBM_H */

@@ -1,0 +1,800 @@
+// C-ABI of the library: context, device memory, step orchestration.
+//
+// One step is two launches on the caller's stream (Methods, the paragraph
+// after eq. potential: the inlet density is found from the streamed knowns,
+// then the pressure condition is applied, then collision):
+//   1. k_inlet_plane   pulled knowns of the inlet sites -> rho_in (FP64)
+//   2. k_stream_collide pull + boundary conditions + BGK + store, f_a -> f_b
+// With pull streaming the "streamed" values of step t are gathers of the
+// stored state, so step 1 needs no grid-wide barrier inside the step kernel.
+// The buffers alternate every step. Runs of steps are captured once per
+// starting buffer as a HIP graph and replayed; the last step of each run
+// also reduces the watchdog observables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fluxlbm.h"
+#include "kernels.h"
+#include "lattice.h"
+
+using namespace flbm;
+
+namespace {
+
+constexpr int HIST_CAP = 8192;
+constexpr int64_t SENT_PAD = 64;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct flbm_ctx {
+    flbm_params p{};
+    LatticeSpec spec;
+    Lattice lat;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+
+    // launch geometry
+    int tiles = 0, nt_in = 0, tout0 = 0, n_bnd = 0, plane_blocks = 0;
+    size_t elem = 4;  // bytes per stored population
+
+    // device memory
+    void *dmem = nullptr;
+    size_t dbytes = 0;
+    bool owned = false, ready = false;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    int32_t *nbr = nullptr;
+    DevState *st = nullptr;
+    double *kpart = nullptr, *bpart_in = nullptr, *bpart_out = nullptr;
+    double *obs_mass = nullptr;
+    float *obs_umax2 = nullptr;
+    uint32_t *obs_bad = nullptr;
+    double *hist = nullptr;
+    double *fields = nullptr;
+
+    // host bookkeeping
+    int64_t steps = 0;
+    int collide = 1;
+    int chunk = 0;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    bool use_graph = true;
+};
+
+namespace {
+
+flbm_status fail(flbm_ctx *c, flbm_status code, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                       \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((c), FLBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+bool is_fp64(const flbm_ctx *c) { return c->p.precision == FLBM_FP64; }
+
+size_t f_bytes(const flbm_ctx *c) { return (size_t)(19 * c->lat.n_pad + SENT_PAD) * c->elem; }
+
+// Carve the device slab. With base == nullptr only the size is computed.
+size_t carve(flbm_ctx *c, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const int64_t npad = c->lat.n_pad;
+    char *f0 = take(f_bytes(c));
+    char *f1 = take(f_bytes(c));
+    char *nb = take((size_t)18 * npad * sizeof(int32_t));
+    char *st = take(sizeof(DevState));
+    char *kp = take(PLANE_MAX_BLOCKS * sizeof(double));
+    char *bi = take((size_t)std::max(1, c->nt_in) * sizeof(double));
+    char *bo = take((size_t)std::max(1, c->tiles - c->tout0) * sizeof(double));
+    char *om = take((size_t)c->tiles * sizeof(double));
+    char *ou = take((size_t)c->tiles * sizeof(float));
+    char *ob = take((size_t)c->tiles * sizeof(uint32_t));
+    char *hi = take((size_t)HIST_CAP * HIST_STRIDE * sizeof(double));
+    char *fl = take((size_t)4 * npad * sizeof(double));
+    if (base) {
+        c->f[0] = f0;
+        c->f[1] = f1;
+        c->nbr = (int32_t *)nb;
+        c->st = (DevState *)st;
+        c->kpart = (double *)kp;
+        c->bpart_in = (double *)bi;
+        c->bpart_out = (double *)bo;
+        c->obs_mass = (double *)om;
+        c->obs_umax2 = (float *)ou;
+        c->obs_bad = (uint32_t *)ob;
+        c->hist = (double *)hi;
+        c->fields = (double *)fl;
+    }
+    return off;
+}
+
+StepArgs step_args(const flbm_ctx *c)
+{
+    StepArgs a{};
+    a.n = c->lat.n;
+    a.npad = c->lat.n_pad;
+    const bool flux = c->p.z_mode == FLBM_Z_FLUX;
+    a.a_in = flux ? c->lat.a_in : 0;
+    a.out0 = flux ? c->lat.n - c->lat.a_out : c->lat.n;
+    a.nt_in = flux ? c->nt_in : 0;
+    a.tout0 = flux ? c->tout0 : c->tiles;
+    a.n_bnd = c->n_bnd;
+    a.hist_cap = HIST_CAP;
+    a.flux_mode = flux;
+    a.rho0 = c->p.rho0;
+    a.inv_rho0 = 1.0 / c->p.rho0;
+    a.st = c->st;
+    a.bpart_in = c->bpart_in;
+    a.bpart_out = c->bpart_out;
+    a.obs_mass = c->obs_mass;
+    a.obs_umax2 = c->obs_umax2;
+    a.obs_bad = c->obs_bad;
+    a.hist = c->hist;
+    return a;
+}
+
+PlaneArgs plane_args(const flbm_ctx *c)
+{
+    PlaneArgs a{};
+    a.npad = c->lat.n_pad;
+    a.a_in = c->lat.a_in;
+    a.hist_cap = HIST_CAP;
+    a.rho0 = c->p.rho0;
+    a.st = c->st;
+    a.kpart = c->kpart;
+    a.hist = c->hist;
+    return a;
+}
+
+ObsArgs obs_args(const flbm_ctx *c, int to_history)
+{
+    ObsArgs a{};
+    a.n = c->lat.n;
+    a.tiles = c->tiles;
+    a.hist_cap = HIST_CAP;
+    a.umax_limit = c->p.umax_limit;
+    a.to_history = to_history;
+    a.raise_flag = c->p.watchdog_every > 0;
+    a.st = c->st;
+    a.obs_mass = c->obs_mass;
+    a.obs_umax2 = c->obs_umax2;
+    a.obs_bad = c->obs_bad;
+    a.hist = c->hist;
+    return a;
+}
+
+// Enqueue one step from buffer `from` on stream s.
+template <typename T>
+void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
+{
+    const T *fin = (const T *)c->f[from];
+    T *fout = (T *)c->f[from ^ 1];
+    if (c->p.z_mode == FLBM_Z_FLUX)
+        hipLaunchKernelGGL(k_inlet_plane<T>, dim3(c->plane_blocks), dim3(BLOCK), 0, s, fin, c->nbr,
+                           plane_args(c));
+    if (obs) {
+        hipLaunchKernelGGL((k_stream_collide<T, true>), dim3(c->tiles), dim3(BLOCK), 0, s, fin, fout,
+                           c->nbr, step_args(c));
+        hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1));
+    } else {
+        hipLaunchKernelGGL((k_stream_collide<T, false>), dim3(c->tiles), dim3(BLOCK), 0, s, fin,
+                           fout, c->nbr, step_args(c));
+    }
+}
+
+void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
+{
+    if (is_fp64(c))
+        launch_step<double>(c, s, from, obs);
+    else
+        launch_step<float>(c, s, from, obs);
+}
+
+void drop_graphs(flbm_ctx *c)
+{
+    for (int i = 0; i < 2; ++i)
+        if (c->graph[i]) {
+            (void)hipGraphExecDestroy(c->graph[i]);
+            c->graph[i] = nullptr;
+        }
+}
+
+flbm_status capture_graph(flbm_ctx *c, int parity)
+{
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < c->chunk; ++i) launch_step_any(c, c->cap_stream, parity ^ (i & 1), i == c->chunk - 1);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (e != hipSuccess) return fail(c, FLBM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph[parity] = nullptr;
+        return fail(c, FLBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return FLBM_OK;
+}
+
+flbm_status reset_state(flbm_ctx *c)
+{
+    DevState h{};
+    h.q_target = c->p.q_target;
+    h.drho_out = c->p.rho_out - 1.0;
+    h.drho_in = 0.0;
+    h.omega = c->collide ? 1.0 / c->p.tau : 0.0;
+    h.step = 0;
+    HIPCHK(c, hipMemcpyAsync(c->st, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->hist, 0xff, (size_t)HIST_CAP * HIST_STRIDE * sizeof(double), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->steps = 0;
+    return FLBM_OK;
+}
+
+template <typename T>
+void launch_fill(flbm_ctx *c, int which, const Dev19 &dev)
+{
+    const int64_t total = 19 * c->lat.n_pad + SENT_PAD;
+    const int blocks = (int)std::min<int64_t>((total + BLOCK - 1) / BLOCK, 65536);
+    hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(BLOCK), 0, c->stream, (T *)c->f[which],
+                       c->lat.n, c->lat.n_pad, total, dev);
+}
+
+flbm_status fill_equilibrium(flbm_ctx *c, double rho, double ux, double uy, double uz)
+{
+    Dev19 dev{};
+    const double uu = ux * ux + uy * uy + uz * uz;
+    for (int q = 0; q < 19; ++q) {
+        const double cu = d3q19::cx[q] * ux + d3q19::cy[q] * uy + d3q19::cz[q] * uz;
+        dev.v[q] = d3q19::weight(q) * ((rho - 1.0) + c->p.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+    Dev19 zero{};
+    for (int w = 0; w < 2; ++w) {
+        if (is_fp64(c))
+            launch_fill<double>(c, w, w == c->cur ? dev : zero);
+        else
+            launch_fill<float>(c, w, w == c->cur ? dev : zero);
+    }
+    HIPCHK(c, hipGetLastError());
+    return reset_state(c);
+}
+
+flbm_status setup_device(flbm_ctx *c, void *mem)
+{
+    c->dmem = mem;
+    carve(c, (char *)mem);
+    HIPCHK(c, hipMemcpyAsync(c->nbr, c->lat.nbr.data(), c->lat.nbr.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->kpart, 0, PLANE_MAX_BLOCKS * sizeof(double), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->ready = true;
+    c->cur = 0;
+    return fill_equilibrium(c, c->p.rho_out, 0.0, 0.0, 0.0);
+}
+
+flbm_status ensure_device(flbm_ctx *c)
+{
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->ready) return FLBM_OK;
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, c->dbytes);
+    if (e != hipSuccess) return fail(c, FLBM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    c->owned = true;
+    return setup_device(c, mem);
+}
+
+flbm_status check_params(const flbm_params *p, std::string &why)
+{
+    if (p->nx < 1 || p->ny < 1 || p->nz < 3) return why = "dimensions must be nx, ny >= 1, nz >= 3", FLBM_EINVAL;
+    if (p->reservoir_layers < 0 || 2 * p->reservoir_layers > p->nz)
+        return why = "reservoir layers exceed the box", FLBM_EINVAL;
+    if (!(p->tau > 0.5)) return why = "tau must exceed 1/2", FLBM_EINVAL;
+    if (!(p->rho0 > 0.0)) return why = "rho0 must be positive", FLBM_EINVAL;
+    if (p->z_mode < FLBM_Z_FLUX || p->z_mode > FLBM_Z_WALL) return why = "unknown z_mode", FLBM_EINVAL;
+    if (p->precision != FLBM_FP64 && p->precision != FLBM_FP32)
+        return why = "precision not available", FLBM_EINVAL;
+    if (p->model != FLBM_BGK) return why = "model not available", FLBM_EINVAL;
+    if (p->watchdog_every < 0) return why = "watchdog_every must be >= 0", FLBM_EINVAL;
+    if (!std::isfinite(p->q_target) || !std::isfinite(p->rho_out) || !(p->rho_out > 0.0))
+        return why = "q_target and rho_out must be finite, rho_out positive", FLBM_EINVAL;
+    return FLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+flbm_status flbm_default_params(flbm_params *p)
+{
+    if (!p) return FLBM_EINVAL;
+    std::memset(p, 0, sizeof(*p));
+    p->periodic_x = 1;
+    p->periodic_y = 1;
+    p->z_mode = FLBM_Z_FLUX;
+    p->precision = FLBM_FP32;
+    p->model = FLBM_BGK;
+    p->watchdog_every = 1000;
+    p->tau = 0.8;
+    p->rho0 = 1.0;
+    p->q_target = 0.0;
+    p->rho_out = 1.0;
+    p->alpha = 0.005;
+    p->beta = 0.7;
+    p->phi_solid = 0.0;
+    p->umax_limit = 0.1;
+    return FLBM_OK;
+}
+
+flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *hip_stream, flbm_ctx **out)
+{
+    if (!solid_mask || !p || !out) return FLBM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    flbm_status rc = check_params(p, why);
+    if (rc != FLBM_OK) return rc;
+    flbm_ctx *c = new (std::nothrow) flbm_ctx();
+    if (!c) return FLBM_ENOMEM;
+    c->p = *p;
+    if (!(c->p.umax_limit > 0.0)) c->p.umax_limit = 0.1;
+    c->spec.nx = p->nx;
+    c->spec.ny = p->ny;
+    c->spec.nz = p->nz;
+    c->spec.periodic_x = p->periodic_x != 0;
+    c->spec.periodic_y = p->periodic_y != 0;
+    c->spec.z_mode = p->z_mode;
+    c->spec.reservoir_layers = p->reservoir_layers;
+    c->stream = (hipStream_t)hip_stream;
+    c->elem = is_fp64(c) ? 8 : 4;
+    int code = FLBM_OK;
+    std::string e = build_lattice(solid_mask, c->spec, c->lat, code);
+    if (!e.empty()) {
+        delete c;
+        return code;
+    }
+    e = check_pull_bijection(c->lat, c->spec);
+    if (!e.empty()) {
+        delete c;
+        return FLBM_EINVAL;
+    }
+    c->tiles = (int)(c->lat.n_pad / BLOCK);
+    const bool flux = p->z_mode == FLBM_Z_FLUX;
+    c->nt_in = flux ? (int)((c->lat.a_in + BLOCK - 1) / BLOCK) : 0;
+    c->tout0 = flux ? (int)((c->lat.n - c->lat.a_out) / BLOCK) : c->tiles;
+    if (flux) {
+        const int overlap = std::max(0, c->nt_in - c->tout0);
+        c->n_bnd = c->nt_in + (c->tiles - c->tout0) - overlap;
+    } else {
+        c->n_bnd = 1;
+    }
+    c->plane_blocks = flux ? (int)std::min<int64_t>((c->lat.a_in + BLOCK - 1) / BLOCK, PLANE_MAX_BLOCKS) : 0;
+    const int w = p->watchdog_every > 0 ? std::min(p->watchdog_every, 256) : 256;
+    c->chunk = std::max(2, w + (w & 1));
+    const char *ng = std::getenv("FLBM_NO_GRAPH");
+    c->use_graph = !(ng && ng[0] == '1');
+    c->dbytes = carve(c, nullptr);
+    // No usable device is not an error yet: the host-side lattice queries
+    // work without one, and the first device call reports the HIP error.
+    if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+    *out = c;
+    return FLBM_OK;
+}
+
+flbm_status flbm_destroy(flbm_ctx *c)
+{
+    if (!c) return FLBM_EINVAL;
+    (void)hipSetDevice(c->device);
+    if (c->ready) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->owned && c->dmem) (void)hipFree(c->dmem);
+    delete c;
+    return FLBM_OK;
+}
+
+flbm_status flbm_device_bytes(const flbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return FLBM_EINVAL;
+    *bytes = c->dbytes;
+    return FLBM_OK;
+}
+
+flbm_status flbm_bind_device_memory(flbm_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c || !dev_ptr) return FLBM_EINVAL;
+    if (c->ready) return fail(c, FLBM_ESTATE, "device memory already in use");
+    if (((uintptr_t)dev_ptr & 255) != 0) return fail(c, FLBM_EINVAL, "device memory must be 256-byte aligned");
+    if (bytes < c->dbytes) return fail(c, FLBM_EBOUND, "device buffer smaller than flbm_device_bytes");
+    HIPCHK(c, hipSetDevice(c->device));
+    c->owned = false;
+    return setup_device(c, dev_ptr);
+}
+
+flbm_status flbm_num_sites(const flbm_ctx *c, int64_t *n_sites, int64_t *a_in, int64_t *a_out)
+{
+    if (!c) return FLBM_EINVAL;
+    if (n_sites) *n_sites = c->lat.n;
+    if (a_in) *a_in = c->lat.a_in;
+    if (a_out) *a_out = c->lat.a_out;
+    return FLBM_OK;
+}
+
+flbm_status flbm_get_site_coords(const flbm_ctx *c, int32_t *xyz)
+{
+    if (!c || !xyz) return FLBM_EINVAL;
+    std::memcpy(xyz, c->lat.coords.data(), c->lat.coords.size() * sizeof(int32_t));
+    return FLBM_OK;
+}
+
+flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr)
+{
+    if (!c || !nbr) return FLBM_EINVAL;
+    const int64_t n = c->lat.n, npad = c->lat.n_pad;
+    for (int q = 0; q < 18; ++q)
+        std::memcpy(nbr + q * n, c->lat.nbr.data() + q * npad, n * sizeof(int32_t));
+    return FLBM_OK;
+}
+
+flbm_status flbm_state_bytes(const flbm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return FLBM_EINVAL;
+    *bytes = (size_t)19 * c->lat.n_pad * c->elem + sizeof(int64_t);
+    return FLBM_OK;
+}
+
+flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes)
+{
+    if (!c || !host) return FLBM_EINVAL;
+    const size_t fb = (size_t)19 * c->lat.n_pad * c->elem;
+    if (bytes < fb + sizeof(int64_t)) return fail(c, FLBM_EBOUND, "host buffer too small");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(host, c->f[c->cur], fb, hipMemcpyDeviceToHost));
+    std::memcpy((char *)host + fb, &c->steps, sizeof(int64_t));
+    return FLBM_OK;
+}
+
+flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
+{
+    if (!c || !host) return FLBM_EINVAL;
+    const size_t fb = (size_t)19 * c->lat.n_pad * c->elem;
+    if (bytes < fb + sizeof(int64_t)) return fail(c, FLBM_EBOUND, "host buffer too small");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->f[c->cur], host, fb, hipMemcpyHostToDevice));
+    rc = reset_state(c);
+    if (rc) return rc;
+    int64_t steps = 0;
+    std::memcpy(&steps, (const char *)host + fb, sizeof(int64_t));
+    // Restore the step counter on both sides so history slots line up.
+    c->steps = steps;
+    HIPCHK(c, hipMemcpy(&c->st->step, &steps, sizeof(int64_t), hipMemcpyHostToDevice));
+    return FLBM_OK;
+}
+
+flbm_status flbm_init_equilibrium(flbm_ctx *c, double rho, double ux, double uy, double uz)
+{
+    if (!c) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    return fill_equilibrium(c, rho, ux, uy, uz);
+}
+
+flbm_status flbm_set_target_flux(flbm_ctx *c, double q_target)
+{
+    if (!c || !std::isfinite(q_target)) return FLBM_EINVAL;
+    c->p.q_target = q_target;
+    if (!c->ready) return FLBM_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, c->stream, &c->st->q_target, q_target);
+    HIPCHK(c, hipGetLastError());
+    return FLBM_OK;
+}
+
+flbm_status flbm_set_outlet_density(flbm_ctx *c, double rho_out)
+{
+    if (!c || !std::isfinite(rho_out) || !(rho_out > 0.0)) return FLBM_EINVAL;
+    c->p.rho_out = rho_out;
+    if (!c->ready) return FLBM_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, c->stream, &c->st->drho_out, rho_out - 1.0);
+    HIPCHK(c, hipGetLastError());
+    return FLBM_OK;
+}
+
+flbm_status flbm_debug_set_collision(flbm_ctx *c, int32_t enabled)
+{
+    if (!c) return FLBM_EINVAL;
+    c->collide = enabled ? 1 : 0;
+    if (!c->ready) return FLBM_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(1), 0, c->stream, &c->st->omega,
+                       c->collide ? 1.0 / c->p.tau : 0.0);
+    HIPCHK(c, hipGetLastError());
+    return FLBM_OK;
+}
+
+flbm_status flbm_step(flbm_ctx *c, int32_t n)
+{
+    if (!c || n < 0) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    int32_t left = n;
+    while (left > 0) {
+        if (c->use_graph && left >= c->chunk) {
+            if (!c->graph[c->cur]) {
+                rc = capture_graph(c, c->cur);
+                if (rc) return rc;
+            }
+            HIPCHK(c, hipGraphLaunch(c->graph[c->cur], c->stream));
+            left -= c->chunk;
+            c->steps += c->chunk;
+        } else {
+            const int k = std::min(left, c->chunk);
+            for (int i = 0; i < k; ++i) {
+                launch_step_any(c, c->stream, c->cur, i == k - 1);
+                c->cur ^= 1;
+            }
+            HIPCHK(c, hipGetLastError());
+            left -= k;
+            c->steps += k;
+        }
+    }
+    return FLBM_OK;
+}
+
+flbm_status flbm_sync(flbm_ctx *c)
+{
+    if (!c) return FLBM_EINVAL;
+    if (!c->ready) return FLBM_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint32_t unstable = 0;
+    HIPCHK(c, hipMemcpy(&unstable, &c->st->unstable, sizeof(unstable), hipMemcpyDeviceToHost));
+    if (unstable) return fail(c, FLBM_EUNSTABLE, "watchdog: non-finite value or |u| above the limit");
+    return FLBM_OK;
+}
+
+flbm_status flbm_history_capacity(const flbm_ctx *c, int32_t *cap)
+{
+    if (!c || !cap) return FLBM_EINVAL;
+    *cap = HIST_CAP;
+    return FLBM_OK;
+}
+
+flbm_status flbm_step_count(const flbm_ctx *c, int64_t *steps)
+{
+    if (!c || !steps) return FLBM_EINVAL;
+    *steps = c->steps;
+    return FLBM_OK;
+}
+
+flbm_status flbm_get_history(flbm_ctx *c, double *buf, int32_t n)
+{
+    if (!c || !buf || n < 0 || n > HIST_CAP || n > c->steps) return FLBM_EINVAL;
+    if (n == 0) return FLBM_OK;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> h((size_t)HIST_CAP * HIST_STRIDE);
+    HIPCHK(c, hipMemcpy(h.data(), c->hist, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t t = c->steps - n + i;  // 0-based step index
+        const double *r = &h[(size_t)(t % HIST_CAP) * HIST_STRIDE];
+        for (int k = 0; k < 5; ++k) buf[5 * (size_t)i + k] = r[k];
+    }
+    return FLBM_OK;
+}
+
+flbm_status flbm_get_boundary(flbm_ctx *c, double *q_in, double *q_out, double *rho_in, double *rho_out)
+{
+    if (!c) return FLBM_EINVAL;
+    if (rho_out) *rho_out = c->p.rho_out;
+    if (c->steps == 0) {
+        if (q_in) *q_in = NAN;
+        if (q_out) *q_out = NAN;
+        if (rho_in) *rho_in = NAN;
+        return FLBM_OK;
+    }
+    double r[5];
+    flbm_status rc = flbm_get_history(c, r, 1);
+    if (rc) return rc;
+    if (rho_in) *rho_in = r[0];
+    if (q_in) *q_in = r[1];
+    if (q_out) *q_out = r[2];
+    return FLBM_OK;
+}
+
+flbm_status flbm_read_fields(flbm_ctx *c, double *rho, double *ux, double *uy, double *uz)
+{
+    if (!c) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    const int64_t n = c->lat.n, npad = c->lat.n_pad;
+    if (is_fp64(c))
+        hipLaunchKernelGGL(k_moments<double>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+                           (const double *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
+    else
+        hipLaunchKernelGGL(k_moments<float>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+                           (const float *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double *dst[4] = {rho, ux, uy, uz};
+    for (int k = 0; k < 4; ++k)
+        if (dst[k]) HIPCHK(c, hipMemcpy(dst[k], c->fields + k * npad, n * sizeof(double), hipMemcpyDeviceToHost));
+    return FLBM_OK;
+}
+
+flbm_status flbm_read_distributions(flbm_ctx *c, double *f)
+{
+    if (!c || !f) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    const int64_t n = c->lat.n, npad = c->lat.n_pad;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (is_fp64(c)) {
+        std::vector<double> h((size_t)19 * npad);
+        HIPCHK(c, hipMemcpy(h.data(), c->f[c->cur], h.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int q = 0; q < 19; ++q)
+            for (int64_t s = 0; s < n; ++s) f[q * n + s] = d3q19::weight(q) + h[q * npad + s];
+    } else {
+        std::vector<float> h((size_t)19 * npad);
+        HIPCHK(c, hipMemcpy(h.data(), c->f[c->cur], h.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (int q = 0; q < 19; ++q)
+            for (int64_t s = 0; s < n; ++s) f[q * n + s] = d3q19::weight(q) + (double)h[q * npad + s];
+    }
+    return FLBM_OK;
+}
+
+flbm_status flbm_write_distributions(flbm_ctx *c, const double *f)
+{
+    if (!c || !f) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    const int64_t n = c->lat.n, npad = c->lat.n_pad;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (is_fp64(c)) {
+        std::vector<double> h((size_t)19 * npad, 0.0);
+        for (int q = 0; q < 19; ++q)
+            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = f[q * n + s] - d3q19::weight(q);
+        HIPCHK(c, hipMemcpy(c->f[c->cur], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> h((size_t)19 * npad, 0.0f);
+        for (int q = 0; q < 19; ++q)
+            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = (float)(f[q * n + s] - d3q19::weight(q));
+        HIPCHK(c, hipMemcpy(c->f[c->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return reset_state(c);
+}
+
+flbm_status flbm_get_observables(flbm_ctx *c, double *mass, double *umax, int32_t *nonfinite)
+{
+    if (!c) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    if (is_fp64(c))
+        hipLaunchKernelGGL(k_state_observables<double>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+                           (const double *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
+                           c->obs_umax2, c->obs_bad);
+    else
+        hipLaunchKernelGGL(k_state_observables<float>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+                           (const float *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
+                           c->obs_umax2, c->obs_bad);
+    hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, c->stream, obs_args(c, 0));
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    DevState h{};
+    HIPCHK(c, hipMemcpy(&h, c->st, sizeof(h), hipMemcpyDeviceToHost));
+    if (mass) *mass = h.obs_mass;
+    if (umax) *umax = h.obs_umax;
+    if (nonfinite) *nonfinite = (int32_t)h.obs_bad;
+    return FLBM_OK;
+}
+
+flbm_status flbm_device_layout(const flbm_ctx *c, void **f_cur, void **nbr, int64_t *n_pad)
+{
+    if (!c) return FLBM_EINVAL;
+    if (f_cur) *f_cur = c->ready ? c->f[c->cur] : nullptr;
+    if (nbr) *nbr = c->ready ? (void *)c->nbr : nullptr;
+    if (n_pad) *n_pad = c->lat.n_pad;
+    return FLBM_OK;
+}
+
+flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, double *ms_step)
+{
+    if (!c || n < 1) return FLBM_EINVAL;
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    hipEvent_t ev[3];
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    double tp = 0.0, ts = 0.0;
+    const bool flux = c->p.z_mode == FLBM_Z_FLUX;
+    for (int32_t i = 0; i < n; ++i) {
+        const int from = c->cur;
+        HIPCHK(c, hipEventRecord(ev[0], c->stream));
+        if (flux) {
+            if (is_fp64(c))
+                hipLaunchKernelGGL(k_inlet_plane<double>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
+                                   (const double *)c->f[from], c->nbr, plane_args(c));
+            else
+                hipLaunchKernelGGL(k_inlet_plane<float>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
+                                   (const float *)c->f[from], c->nbr, plane_args(c));
+        }
+        HIPCHK(c, hipEventRecord(ev[1], c->stream));
+        if (is_fp64(c))
+            hipLaunchKernelGGL((k_stream_collide<double, false>), dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+                               (const double *)c->f[from], (double *)c->f[from ^ 1], c->nbr, step_args(c));
+        else
+            hipLaunchKernelGGL((k_stream_collide<float, false>), dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+                               (const float *)c->f[from], (float *)c->f[from ^ 1], c->nbr, step_args(c));
+        HIPCHK(c, hipEventRecord(ev[2], c->stream));
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipEventSynchronize(ev[2]));
+        float a = 0.f, b = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIPCHK(c, hipEventElapsedTime(&b, ev[1], ev[2]));
+        tp += a;
+        ts += b;
+        c->cur ^= 1;
+        c->steps += 1;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (ms_plane) *ms_plane = tp / n;
+    if (ms_step) *ms_step = ts / n;
+    return FLBM_OK;
+}
+
+flbm_status flbm_copy_kernel(const void *src, void *dst, size_t bytes, void *hip_stream)
+{
+    if (!src || !dst || (bytes & 15) != 0) return FLBM_EINVAL;
+    if ((((uintptr_t)src) & 15) || (((uintptr_t)dst) & 15)) return FLBM_EINVAL;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return FLBM_OK;
+    const int blocks = (int)std::min<int64_t>((n16 + BLOCK - 1) / BLOCK, 256 * 64);
+    hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(BLOCK), 0, (hipStream_t)hip_stream,
+                       (const u32x4 *)src, (u32x4 *)dst, n16);
+    return hipGetLastError() == hipSuccess ? FLBM_OK : FLBM_EHIP;
+}
+
+const char *flbm_status_string(flbm_status s)
+{
+    switch (s) {
+    case FLBM_OK: return "ok";
+    case FLBM_EINVAL: return "invalid argument";
+    case FLBM_ENOINLET: return "no pore site on the inlet plane";
+    case FLBM_ENOMEM: return "out of memory";
+    case FLBM_EHIP: return "HIP runtime error";
+    case FLBM_EUNSTABLE: return "watchdog: unstable state";
+    case FLBM_EINDEX: return "lattice too large for 32-bit indices";
+    case FLBM_EBOUND: return "device buffer too small";
+    case FLBM_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+    }
+}
+
+const char *flbm_last_error(const flbm_ctx *c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

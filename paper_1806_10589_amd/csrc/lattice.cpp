@@ -1,0 +1,183 @@
+// Sparse pore-site lattice builder: solid mask -> site list + int32 pull table.
+#include "lattice.h"
+
+#include <algorithm>
+#include <thread>
+
+#include "../../include/fluxlbm.h"
+#include "d3q19.h"
+
+namespace flbm {
+
+int64_t padded_sites(int64_t n) { return ((n + 255) / 256) * 256; }
+
+namespace {
+
+template <class F>
+void parallel_for(int64_t begin, int64_t end, F &&fn)
+{
+    int64_t count = end - begin;
+    if (count <= 0) return;
+    unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    int64_t nt = std::min<int64_t>(std::min<unsigned>(hw, 16u), count);
+    if (nt <= 1 || count < 4) {
+        fn(begin, end);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (count + nt - 1) / nt;
+    for (int64_t t = 0; t < nt; ++t) {
+        int64_t b = begin + t * chunk, e = std::min(end, b + chunk);
+        if (b >= e) break;
+        th.emplace_back([&fn, b, e] { fn(b, e); });
+    }
+    for (auto &t : th) t.join();
+}
+
+}  // namespace
+
+std::string build_lattice(const uint8_t *solid_in, const LatticeSpec &spec, Lattice &L, int &code)
+{
+    const int nx = spec.nx, ny = spec.ny, nz = spec.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t ncell = plane * nz;
+    code = FLBM_OK;
+
+    auto is_solid = [&](int x, int y, int z) -> bool {
+        if (z < spec.reservoir_layers || z >= nz - spec.reservoir_layers) return false;
+        return solid_in[(int64_t)z * plane + (int64_t)y * nx + x] != 0;
+    };
+
+    // Site numbering in raster order; per-plane counts give plane offsets so
+    // planes can be numbered in parallel.
+    std::vector<int64_t> plane_count(nz, 0);
+    parallel_for(0, nz, [&](int64_t z0, int64_t z1) {
+        for (int64_t z = z0; z < z1; ++z) {
+            int64_t c = 0;
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) c += !is_solid(x, y, (int)z);
+            plane_count[z] = c;
+        }
+    });
+    std::vector<int64_t> plane_off(nz + 1, 0);
+    for (int z = 0; z < nz; ++z) plane_off[z + 1] = plane_off[z] + plane_count[z];
+    const int64_t n = plane_off[nz];
+    L.n = n;
+    L.n_pad = padded_sites(n);
+    L.a_in = plane_count[0];
+    L.a_out = plane_count[nz - 1];
+    L.sentinel = 19 * L.n_pad;
+    if (n == 0) {
+        code = FLBM_EINVAL;
+        return "the mask has no pore site";
+    }
+    if (spec.z_mode == FLBM_Z_FLUX && L.a_in == 0) {
+        code = FLBM_ENOINLET;
+        return "no pore site on the inlet plane z = 0";
+    }
+    // Largest index: the sentinel plus the 64-element zero pad behind it.
+    if (19 * L.n_pad + 64 > (int64_t)INT32_MAX) {
+        code = FLBM_EINDEX;
+        return "lattice too large for 32-bit pull indices";
+    }
+
+    std::vector<int32_t> site_of;
+    try {
+        site_of.assign(ncell, -1);
+        L.coords.assign(3 * n, 0);
+        L.nbr.assign(18 * L.n_pad, 0);
+    } catch (const std::bad_alloc &) {
+        code = FLBM_ENOMEM;
+        return "host allocation failed while building the lattice";
+    }
+    parallel_for(0, nz, [&](int64_t z0, int64_t z1) {
+        for (int64_t z = z0; z < z1; ++z) {
+            int64_t s = plane_off[z];
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    if (is_solid(x, y, (int)z)) continue;
+                    site_of[z * plane + (int64_t)y * nx + x] = (int32_t)s;
+                    L.coords[3 * s + 0] = x;
+                    L.coords[3 * s + 1] = y;
+                    L.coords[3 * s + 2] = (int32_t)z;
+                    ++s;
+                }
+        }
+    });
+
+    const int64_t npad = L.n_pad;
+    const int32_t sentinel = (int32_t)L.sentinel;
+    parallel_for(0, n, [&](int64_t s0, int64_t s1) {
+        for (int64_t s = s0; s < s1; ++s) {
+            const int x = L.coords[3 * s], y = L.coords[3 * s + 1], z = L.coords[3 * s + 2];
+            for (int q = 1; q < 19; ++q) {
+                int sx = x - d3q19::cx[q], sy = y - d3q19::cy[q], sz = z - d3q19::cz[q];
+                int32_t idx;
+                bool bounce = false;
+                if (sz < 0 || sz >= nz) {
+                    if (spec.z_mode == FLBM_Z_PERIODIC) {
+                        sz = (sz + nz) % nz;
+                    } else if (spec.z_mode == FLBM_Z_WALL) {
+                        bounce = true;
+                    } else {
+                        L.nbr[(q - 1) * npad + s] = sentinel;
+                        continue;
+                    }
+                }
+                if (sx < 0 || sx >= nx) {
+                    if (spec.periodic_x) sx = (sx + nx) % nx;
+                    else bounce = true;
+                }
+                if (sy < 0 || sy >= ny) {
+                    if (spec.periodic_y) sy = (sy + ny) % ny;
+                    else bounce = true;
+                }
+                if (!bounce) {
+                    int32_t src = site_of[(int64_t)sz * plane + (int64_t)sy * nx + sx];
+                    if (src < 0) bounce = true;
+                    else idx = (int32_t)(q * npad + src);
+                }
+                if (bounce) idx = (int32_t)(d3q19::opp(q) * npad + s);
+                L.nbr[(q - 1) * npad + s] = idx;
+            }
+        }
+    });
+    // Padding sites read their own (zero) slots so any thread may load them.
+    for (int64_t s = n; s < npad; ++s)
+        for (int q = 1; q < 19; ++q) L.nbr[(q - 1) * npad + s] = (int32_t)(q * npad + s);
+    return std::string();
+}
+
+std::string check_pull_bijection(const Lattice &L, const LatticeSpec &spec)
+{
+    const int64_t n = L.n, npad = L.n_pad;
+    std::vector<uint8_t> seen((size_t)19 * n, 0);
+    for (int64_t s = 0; s < n; ++s) seen[s] = 1;  // q = 0 reads its own slot
+    for (int q = 1; q < 19; ++q)
+        for (int64_t s = 0; s < n; ++s) {
+            int64_t idx = L.nbr[(q - 1) * npad + s];
+            if (idx == L.sentinel) {
+                bool ok = spec.z_mode == FLBM_Z_FLUX &&
+                          ((L.coords[3 * s + 2] == 0 && d3q19::cz[q] == 1) ||
+                           (L.coords[3 * s + 2] == spec.nz - 1 && d3q19::cz[q] == -1));
+                if (!ok) return "sentinel outside a boundary unknown";
+                continue;
+            }
+            int64_t qq = idx / npad, ss = idx % npad;
+            if (qq < 0 || qq >= 19 || ss >= n) return "pull index out of range";
+            uint8_t &m = seen[qq * n + ss];
+            if (m) return "two pulls read one slot";
+            m = 1;
+        }
+    for (int q = 0; q < 19; ++q)
+        for (int64_t s = 0; s < n; ++s) {
+            if (seen[q * n + s]) continue;
+            int z = L.coords[3 * s + 2];
+            bool leaves = spec.z_mode == FLBM_Z_FLUX &&
+                          ((z == 0 && d3q19::cz[q] == -1) || (z == spec.nz - 1 && d3q19::cz[q] == 1));
+            if (!leaves) return "a population is never read";
+        }
+    return std::string();
+}
+
+}  // namespace flbm

@@ -1,0 +1,429 @@
+"""Thin ctypes binding of ``libfluxlbm.so`` (see ``include/fluxlbm.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. PyTorch provides the device memory (one ``uint8`` tensor bound
+to the context) and the stream (torch's current stream). There is no CPU
+fallback: if the library is missing, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfluxlbm.so")
+
+FLBM_OK = 0
+FLBM_EINVAL = -1
+FLBM_ENOINLET = -2
+FLBM_ENOMEM = -3
+FLBM_EHIP = -4
+FLBM_EUNSTABLE = -5
+FLBM_EINDEX = -6
+FLBM_EBOUND = -7
+FLBM_ESTATE = -8
+
+FLBM_FP64, FLBM_FP32, FLBM_FP16DEV = 0, 1, 2
+FLBM_BGK, FLBM_COLOUR = 0, 1
+FLBM_Z_FLUX, FLBM_Z_PERIODIC, FLBM_Z_WALL = 0, 1, 2
+
+PRECISIONS = {"fp64": FLBM_FP64, "fp32": FLBM_FP32, "fp16dev": FLBM_FP16DEV}
+MODELS = {"bgk": FLBM_BGK, "colour": FLBM_COLOUR}
+
+
+class FlbmError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: status {status}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+class flbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("periodic_x", ctypes.c_int32), ("periodic_y", ctypes.c_int32),
+        ("z_mode", ctypes.c_int32), ("reservoir_layers", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("model", ctypes.c_int32),
+        ("watchdog_every", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("q_target", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+        ("phi_solid", ctypes.c_double), ("umax_limit", ctypes.c_double),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_D = ctypes.c_double
+_DP = ctypes.POINTER(ctypes.c_double)
+
+# name -> argtypes (all return int32 status unless listed in _RESTYPES)
+_SIGS = {
+    "flbm_default_params": [ctypes.POINTER(flbm_params)],
+    "flbm_create": [_P, ctypes.POINTER(flbm_params), _P, ctypes.POINTER(_P)],
+    "flbm_destroy": [_P],
+    "flbm_device_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "flbm_bind_device_memory": [_P, _P, ctypes.c_size_t],
+    "flbm_num_sites": [_P, _I64P, _I64P, _I64P],
+    "flbm_get_site_coords": [_P, _P],
+    "flbm_init_equilibrium": [_P, _D, _D, _D, _D],
+    "flbm_set_target_flux": [_P, _D],
+    "flbm_set_outlet_density": [_P, _D],
+    "flbm_step": [_P, _I32],
+    "flbm_sync": [_P],
+    "flbm_get_boundary": [_P, _DP, _DP, _DP, _DP],
+    "flbm_get_history": [_P, _P, _I32],
+    "flbm_history_capacity": [_P, ctypes.POINTER(_I32)],
+    "flbm_step_count": [_P, _I64P],
+    "flbm_read_fields": [_P, _P, _P, _P, _P],
+    "flbm_read_distributions": [_P, _P],
+    "flbm_write_distributions": [_P, _P],
+    "flbm_get_pull_table": [_P, _P],
+    "flbm_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "flbm_save_state": [_P, _P, ctypes.c_size_t],
+    "flbm_load_state": [_P, _P, ctypes.c_size_t],
+    "flbm_debug_set_collision": [_P, _I32],
+    "flbm_get_observables": [_P, _DP, _DP, ctypes.POINTER(_I32)],
+    "flbm_device_layout": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I64P],
+    "flbm_profile_kernels": [_P, _I32, _DP, _DP],
+    "flbm_copy_kernel": [_P, _P, ctypes.c_size_t, _P],
+    "flbm_status_string": [_I32],
+    "flbm_last_error": [_P],
+}
+_RESTYPES = {"flbm_status_string": ctypes.c_char_p, "flbm_last_error": ctypes.c_char_p}
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libfluxlbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library {path} is missing: build it with `python -m paper_1806_10589_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, argtypes in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argtypes
+        fn.restype = _RESTYPES.get(name, _I32)
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(rc: int, where: str, ctx=None):
+    if rc != FLBM_OK:
+        lib = load_library()
+        detail = lib.flbm_status_string(rc).decode()
+        if ctx:
+            extra = lib.flbm_last_error(ctx)
+            if extra:
+                detail += ": " + extra.decode()
+        raise FlbmError(rc, where, detail)
+
+
+# ------------------------------------------------------------------ C-ABI names
+
+def flbm_default_params() -> flbm_params:
+    p = flbm_params()
+    _check(load_library().flbm_default_params(ctypes.byref(p)), "flbm_default_params")
+    return p
+
+
+def flbm_create(mask: np.ndarray, params: flbm_params, stream: int | None = None):
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    ctx = _P()
+    _check(load_library().flbm_create(mask.ctypes.data, ctypes.byref(params), stream or None,
+                                      ctypes.byref(ctx)), "flbm_create")
+    return ctx
+
+
+def flbm_destroy(ctx) -> None:
+    _check(load_library().flbm_destroy(ctx), "flbm_destroy")
+
+
+def flbm_device_bytes(ctx) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().flbm_device_bytes(ctx, ctypes.byref(v)), "flbm_device_bytes", ctx)
+    return int(v.value)
+
+
+def flbm_bind_device_memory(ctx, dev_ptr: int, nbytes: int) -> None:
+    _check(load_library().flbm_bind_device_memory(ctx, dev_ptr, nbytes), "flbm_bind_device_memory", ctx)
+
+
+def flbm_num_sites(ctx):
+    n, a, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().flbm_num_sites(ctx, ctypes.byref(n), ctypes.byref(a), ctypes.byref(b)),
+           "flbm_num_sites", ctx)
+    return int(n.value), int(a.value), int(b.value)
+
+
+def flbm_get_site_coords(ctx, n_sites: int) -> np.ndarray:
+    out = np.empty((n_sites, 3), np.int32)
+    _check(load_library().flbm_get_site_coords(ctx, out.ctypes.data), "flbm_get_site_coords", ctx)
+    return out
+
+
+def flbm_init_equilibrium(ctx, rho=1.0, ux=0.0, uy=0.0, uz=0.0) -> None:
+    _check(load_library().flbm_init_equilibrium(ctx, rho, ux, uy, uz), "flbm_init_equilibrium", ctx)
+
+
+def flbm_set_target_flux(ctx, q: float) -> None:
+    _check(load_library().flbm_set_target_flux(ctx, q), "flbm_set_target_flux", ctx)
+
+
+def flbm_set_outlet_density(ctx, rho: float) -> None:
+    _check(load_library().flbm_set_outlet_density(ctx, rho), "flbm_set_outlet_density", ctx)
+
+
+def flbm_step(ctx, n: int) -> None:
+    _check(load_library().flbm_step(ctx, int(n)), "flbm_step", ctx)
+
+
+def flbm_sync(ctx) -> int:
+    """Returns the status (FLBM_OK or FLBM_EUNSTABLE); raises on other errors."""
+    rc = load_library().flbm_sync(ctx)
+    if rc not in (FLBM_OK, FLBM_EUNSTABLE):
+        _check(rc, "flbm_sync", ctx)
+    return rc
+
+
+def flbm_get_boundary(ctx):
+    v = [_D() for _ in range(4)]
+    _check(load_library().flbm_get_boundary(ctx, *[ctypes.byref(x) for x in v]), "flbm_get_boundary", ctx)
+    return tuple(float(x.value) for x in v)
+
+
+def flbm_get_history(ctx, n: int) -> np.ndarray:
+    out = np.empty((n, 5), np.float64)
+    _check(load_library().flbm_get_history(ctx, out.ctypes.data, int(n)), "flbm_get_history", ctx)
+    return out
+
+
+def flbm_history_capacity(ctx) -> int:
+    v = _I32()
+    _check(load_library().flbm_history_capacity(ctx, ctypes.byref(v)), "flbm_history_capacity", ctx)
+    return int(v.value)
+
+
+def flbm_step_count(ctx) -> int:
+    v = ctypes.c_int64()
+    _check(load_library().flbm_step_count(ctx, ctypes.byref(v)), "flbm_step_count", ctx)
+    return int(v.value)
+
+
+def flbm_read_fields(ctx, n_sites: int):
+    arrs = [np.empty(n_sites, np.float64) for _ in range(4)]
+    _check(load_library().flbm_read_fields(ctx, *[a.ctypes.data for a in arrs]), "flbm_read_fields", ctx)
+    return tuple(arrs)
+
+
+def flbm_read_distributions(ctx, n_sites: int) -> np.ndarray:
+    out = np.empty((19, n_sites), np.float64)
+    _check(load_library().flbm_read_distributions(ctx, out.ctypes.data), "flbm_read_distributions", ctx)
+    return out
+
+
+def flbm_write_distributions(ctx, f: np.ndarray) -> None:
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    _check(load_library().flbm_write_distributions(ctx, f.ctypes.data), "flbm_write_distributions", ctx)
+
+
+def flbm_get_pull_table(ctx, n_sites: int) -> np.ndarray:
+    out = np.empty((18, n_sites), np.int32)
+    _check(load_library().flbm_get_pull_table(ctx, out.ctypes.data), "flbm_get_pull_table", ctx)
+    return out
+
+
+def flbm_state_bytes(ctx) -> int:
+    v = ctypes.c_size_t()
+    _check(load_library().flbm_state_bytes(ctx, ctypes.byref(v)), "flbm_state_bytes", ctx)
+    return int(v.value)
+
+
+def flbm_save_state(ctx) -> bytes:
+    n = flbm_state_bytes(ctx)
+    buf = ctypes.create_string_buffer(n)
+    _check(load_library().flbm_save_state(ctx, buf, n), "flbm_save_state", ctx)
+    return buf.raw
+
+
+def flbm_load_state(ctx, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(load_library().flbm_load_state(ctx, buf, len(blob)), "flbm_load_state", ctx)
+
+
+def flbm_debug_set_collision(ctx, enabled: bool) -> None:
+    _check(load_library().flbm_debug_set_collision(ctx, int(bool(enabled))), "flbm_debug_set_collision", ctx)
+
+
+def flbm_get_observables(ctx):
+    m, u, b = _D(), _D(), _I32()
+    _check(load_library().flbm_get_observables(ctx, ctypes.byref(m), ctypes.byref(u), ctypes.byref(b)),
+           "flbm_get_observables", ctx)
+    return float(m.value), float(u.value), int(b.value)
+
+
+def flbm_device_layout(ctx):
+    f, nb, npad = _P(), _P(), ctypes.c_int64()
+    _check(load_library().flbm_device_layout(ctx, ctypes.byref(f), ctypes.byref(nb), ctypes.byref(npad)),
+           "flbm_device_layout", ctx)
+    return f.value, nb.value, int(npad.value)
+
+
+def flbm_profile_kernels(ctx, n: int):
+    a, b = _D(), _D()
+    _check(load_library().flbm_profile_kernels(ctx, int(n), ctypes.byref(a), ctypes.byref(b)),
+           "flbm_profile_kernels", ctx)
+    return float(a.value), float(b.value)
+
+
+def flbm_copy_kernel(src: int, dst: int, nbytes: int, stream: int | None = None) -> None:
+    _check(load_library().flbm_copy_kernel(src, dst, nbytes, stream or None), "flbm_copy_kernel")
+
+
+# ------------------------------------------------------------------ convenience
+
+class Lattice:
+    """A context whose device memory is one torch ``uint8`` tensor and whose
+    stream is torch's current stream on ``device``.
+
+    Parameters mirror ``flbm_params``; the mask is ``uint8 (nz, ny, nx)``.
+    """
+
+    def __init__(self, mask: np.ndarray, *, tau: float = 0.8, q_target: float = 0.0,
+                 rho_out: float = 1.0, rho0: float = 1.0, precision: str = "fp32",
+                 model: str = "bgk", periodic_x: bool = True, periodic_y: bool = True,
+                 z_mode: int = FLBM_Z_FLUX, reservoir_layers: int = 0,
+                 watchdog_every: int = 1000, umax_limit: float = 0.1, alpha: float | None = None,
+                 beta: float | None = None, phi_solid: float | None = None,
+                 device: str = "cuda:0"):
+        import torch
+
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        if mask.ndim != 3:
+            raise ValueError("mask must be (nz, ny, nx)")
+        p = flbm_default_params()
+        p.nz, p.ny, p.nx = mask.shape
+        p.periodic_x, p.periodic_y = int(periodic_x), int(periodic_y)
+        p.z_mode = int(z_mode)
+        p.reservoir_layers = int(reservoir_layers)
+        p.precision = PRECISIONS[precision]
+        p.model = MODELS[model]
+        p.watchdog_every = int(watchdog_every)
+        p.tau, p.rho0, p.q_target, p.rho_out = float(tau), float(rho0), float(q_target), float(rho_out)
+        p.umax_limit = float(umax_limit)
+        if alpha is not None:
+            p.alpha = float(alpha)
+        if beta is not None:
+            p.beta = float(beta)
+        if phi_solid is not None:
+            p.phi_solid = float(phi_solid)
+        self.params = p
+        self.device = torch.device(device)
+        self._torch = torch
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ctx = flbm_create(mask, p, self.stream.cuda_stream)
+            try:
+                self.n_sites, self.a_in, self.a_out = flbm_num_sites(self.ctx)
+                nbytes = flbm_device_bytes(self.ctx)
+                self._mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+                base = self._mem.data_ptr()
+                aligned = (base + 255) // 256 * 256
+                flbm_bind_device_memory(self.ctx, aligned, nbytes)
+            except Exception:
+                flbm_destroy(self.ctx)
+                self.ctx = None
+                raise
+        self.device_bytes = nbytes
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            flbm_destroy(self.ctx)
+            self.ctx = None
+            self._mem = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # thin forwards -------------------------------------------------------------
+    def coords(self) -> np.ndarray:
+        return flbm_get_site_coords(self.ctx, self.n_sites)
+
+    def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0, uz=0.0):
+        flbm_init_equilibrium(self.ctx, rho, ux, uy, uz)
+
+    def set_target_flux(self, q):
+        flbm_set_target_flux(self.ctx, q)
+
+    def set_outlet_density(self, rho):
+        flbm_set_outlet_density(self.ctx, rho)
+
+    def step(self, n=1):
+        flbm_step(self.ctx, n)
+
+    def sync(self) -> int:
+        return flbm_sync(self.ctx)
+
+    def boundary(self):
+        return flbm_get_boundary(self.ctx)
+
+    def history(self, n):
+        return flbm_get_history(self.ctx, n)
+
+    @property
+    def step_count(self):
+        return flbm_step_count(self.ctx)
+
+    def fields(self):
+        return flbm_read_fields(self.ctx, self.n_sites)
+
+    def read_distributions(self):
+        return flbm_read_distributions(self.ctx, self.n_sites)
+
+    def write_distributions(self, f):
+        flbm_write_distributions(self.ctx, f)
+
+    def pull_table(self):
+        return flbm_get_pull_table(self.ctx, self.n_sites)
+
+    def save_state(self) -> bytes:
+        return flbm_save_state(self.ctx)
+
+    def load_state(self, blob: bytes):
+        flbm_load_state(self.ctx, blob)
+
+    def set_collision(self, enabled: bool):
+        flbm_debug_set_collision(self.ctx, enabled)
+
+    def observables(self):
+        return flbm_get_observables(self.ctx)
+
+    def profile_kernels(self, n):
+        return flbm_profile_kernels(self.ctx, n)
+
+    def layout(self):
+        return flbm_device_layout(self.ctx)
