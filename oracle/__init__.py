@@ -5,7 +5,11 @@ baseline leg of ``bench.py`` may import this package. It shares no code with
 the HIP library (``paper_1806_10589_amd``) and never imports it.
 """
 from .oracle import (  # noqa: F401
+    OracleColour,
     OracleLattice,
+    mrt_collide_site,
+    mrt_collide_site_rates,
+    mrt_matrix,
     build,
     equilibrium,
     inlet_bc_site,

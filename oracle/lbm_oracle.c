@@ -330,24 +330,26 @@ void orc_fields(const orc_lattice *L, double *rho, double *ux, double *uy, doubl
     }
 }
 
-/* a. Push streaming with halfway bounce-back. Every slot of ft that no
- * population reaches is left NaN: those are exactly the boundary unknowns,
+/* a. Push streaming with halfway bounce-back of the first nq velocities
+ * (19 for D3Q19; 7 for the D3Q7 mass transport, whose velocities are q = 0..6
+ * of the same set, App. A), src and dst with stride nq. Every slot of dst that
+ * no population reaches is left NaN: those are exactly the boundary unknowns,
  * which the inlet/outlet conditions fill; a NaN surviving them would expose a
  * streaming error. */
-static void stream_push(orc_lattice *L)
+static void stream_push_n(const orc_lattice *L, const double *src, double *dst, int nq)
 {
     const int nx = L->nx, ny = L->ny, nz = L->nz;
     const double nan_value = NAN;
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < L->ncell; ++c)
-        for (int q = 0; q < Q19; ++q) L->ft[c * Q19 + q] = L->solid[c] ? 0.0 : nan_value;
+        for (int q = 0; q < nq; ++q) dst[c * nq + q] = L->solid[c] ? 0.0 : nan_value;
 #pragma omp parallel for schedule(static)
     for (int z = 0; z < nz; ++z)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long c = cell_index(L, x, y, z);
                 if (L->solid[c]) continue;
-                for (int q = 0; q < Q19; ++q) {
+                for (int q = 0; q < nq; ++q) {
                     int tx = x + CX[q], ty = y + CY[q], tz = z + CZ[q];
                     int leaves = 0, blocked = 0;
                     /* The z faces take precedence: a population that crosses
@@ -374,14 +376,16 @@ static void stream_push(orc_lattice *L)
                             blocked = 1;
                     }
                     if (!blocked && L->solid[cell_index(L, tx, ty, tz)]) blocked = 1;
-                    double v = L->f[c * Q19 + q];
+                    double v = src[c * nq + q];
                     if (blocked)
-                        L->ft[c * Q19 + OPP[q]] = v;
+                        dst[c * nq + OPP[q]] = v;
                     else
-                        L->ft[cell_index(L, tx, ty, tz) * Q19 + q] = v;
+                        dst[cell_index(L, tx, ty, tz) * nq + q] = v;
                 }
             }
 }
+
+static void stream_push(orc_lattice *L) { stream_push_n(L, L->f, L->ft, Q19); }
 
 /* d. BGK collision with relaxation time tau: f <- f - (f - f_eq)/tau
  * (Methods: nu = c_s^2 (tau - 1/2)). */
@@ -403,15 +407,14 @@ static void collide_bgk(orc_lattice *L)
     }
 }
 
-/* One time step. hist (may be NULL) receives, in this order:
- * rho_in, Q_in, Q_out, total mass, max |u|.
- * Returns 0, or -1 if a slot was left unset (a streaming error). */
-static int step_once(orc_lattice *L, double *hist)
+/* b, c. The flux inlet and the pressure outlet on the streamed values ft.
+ * uz_in / uz_out (may be NULL) receive the boundary velocity of every site of
+ * plane z = 0 / z = nz-1 (index x + nx*y; solid sites untouched). */
+static void apply_momentum_bc(orc_lattice *L, double *uz_in, double *uz_out, double *rho_in_out,
+                              double *q_in_out, double *q_out_out)
 {
     const int nx = L->nx, ny = L->ny, nz = L->nz;
     const double rho0 = L->rho0;
-    stream_push(L);
-
     double rho_in = NAN, q_in = 0.0, q_out = 0.0;
     if (L->z_mode == ORC_Z_FLUX) {
         /* b. eq. potential: rho = rho0 Q_z / A + (1/A) sum_i K_i over the
@@ -428,48 +431,78 @@ static int step_once(orc_lattice *L, double *hist)
             for (int x = 0; x < nx; ++x) {
                 long c = cell_index(L, x, y, 0);
                 if (L->solid[c]) continue;
-                q_in += orc_inlet_bc_site(&L->ft[c * Q19], rho_in, rho0);
+                double uz = orc_inlet_bc_site(&L->ft[c * Q19], rho_in, rho0);
+                if (uz_in) uz_in[x + nx * y] = uz;
+                q_in += uz;
             }
         /* c. pressure outlet with rho_out. */
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long c = cell_index(L, x, y, nz - 1);
                 if (L->solid[c]) continue;
-                q_out += orc_outlet_bc_site(&L->ft[c * Q19], L->rho_out, rho0);
+                double uz = orc_outlet_bc_site(&L->ft[c * Q19], L->rho_out, rho0);
+                if (uz_out) uz_out[x + nx * y] = uz;
+                q_out += uz;
             }
     }
+    *rho_in_out = rho_in;
+    *q_in_out = q_in;
+    *q_out_out = q_out;
+}
 
+/* 1 if a pore slot of a (stride nq) is NaN: a slot no population reached. */
+static int any_unset(const orc_lattice *L, const double *a, int nq)
+{
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (long c = 0; c < L->ncell; ++c) {
         if (L->solid[c]) continue;
-        for (int q = 0; q < Q19; ++q)
-            if (isnan(L->ft[c * Q19 + q])) bad |= 1;
+        for (int q = 0; q < nq; ++q)
+            if (isnan(a[c * nq + q])) bad |= 1;
     }
+    return bad;
+}
 
-    double mass = 0.0, umax = 0.0;
-    if (hist) {
-        /* e. max |u| over the post-boundary moments (collision keeps them). */
-        for (long c = 0; c < L->ncell; ++c) {
-            if (L->solid[c]) continue;
-            double rho, jx, jy, jz;
-            moments(&L->ft[c * Q19], &rho, &jx, &jy, &jz);
-            double u = sqrt(jx * jx + jy * jy + jz * jz) / rho0;
-            if (u > umax || isnan(u)) umax = u;
-        }
+/* max |u| over the pore sites of a state (collision keeps rho and j). */
+static double max_speed(const orc_lattice *L, const double *f)
+{
+    double umax = 0.0;
+    for (long c = 0; c < L->ncell; ++c) {
+        if (L->solid[c]) continue;
+        double rho, jx, jy, jz;
+        moments(&f[c * Q19], &rho, &jx, &jy, &jz);
+        double u = sqrt(jx * jx + jy * jy + jz * jz) / L->rho0;
+        if (u > umax || isnan(u)) umax = u;
     }
+    return umax;
+}
 
+static double total_mass(const orc_lattice *L, const double *a, int nq)
+{
+    double m = 0.0;
+    for (long c = 0; c < L->ncell; ++c) {
+        if (L->solid[c]) continue;
+        for (int q = 0; q < nq; ++q) m += a[c * nq + q];
+    }
+    return m;
+}
+
+/* One time step. hist (may be NULL) receives, in this order:
+ * rho_in, Q_in, Q_out, total mass, max |u|.
+ * Returns 0, or -1 if a slot was left unset (a streaming error). */
+static int step_once(orc_lattice *L, double *hist)
+{
+    stream_push(L);
+    double rho_in, q_in, q_out;
+    apply_momentum_bc(L, NULL, NULL, &rho_in, &q_in, &q_out);
+    int bad = any_unset(L, L->ft, Q19);
+    double umax = hist ? max_speed(L, L->ft) : 0.0;
     collide_bgk(L);
-
     if (hist) {
-        for (long c = 0; c < L->ncell; ++c) {
-            if (L->solid[c]) continue;
-            for (int q = 0; q < Q19; ++q) mass += L->ft[c * Q19 + q];
-        }
         hist[0] = rho_in;
         hist[1] = q_in;
         hist[2] = q_out;
-        hist[3] = mass;
+        hist[3] = total_mass(L, L->ft, Q19);
         hist[4] = umax;
     }
     double *t = L->f;
@@ -488,3 +521,420 @@ int orc_step(orc_lattice *L, int n, double *hist)
     }
     return 0;
 }
+
+/* ======================================================================
+ * Two-fluid colour-gradient model (Appendix A).
+ *
+ * Momentum: D3Q19 MRT. Moments m = M f in the basis of d'Humieres et al.
+ * (2002), in the order Appendix A lists them:
+ *   (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww,
+ *    p_xy, p_yz, p_xz, m_x, m_y, m_z),
+ * built here from the basis polynomials of that paper (the matrix is not
+ * printed in the text). Relaxation m* = m - S (m - m_eq) with
+ *   S = diag(0, s_e, s_eps, 0, s_q, 0, s_q, 0, s_q, s_nu, s_pi, s_nu, s_pi,
+ *            s_nu, s_nu, s_nu, s_m, s_m, s_m),
+ *   s_e = s_eps = s_pi = s_nu = 1/tau,  s_q = s_m = 8 (2 - s_nu)/(8 - s_nu).
+ * Equilibrium moments: the projections M f_eq(rho, j) plus the interfacial
+ * stress of Appendix A, alpha |C| times
+ *   e: 19 (the paper's e is the density-independent part scaled by 1/19),
+ *   3p_xx: (2n_x^2 - n_y^2 - n_z^2)/2,  p_ww: (n_y^2 - n_z^2)/2,
+ *   p_xy: n_x n_y/2,  p_yz: n_y n_z/2,  p_xz: n_x n_z/2.
+ * C = grad phi by the isotropic stencil C = 3 sum_q w_q xi_q phi(x + xi_q),
+ * n = C/|C| (n = 0 where |C| <= 1e-6).
+ *
+ * Mass transport: D3Q7 (q = 0..6 of the same velocity set, weights 1/3 and
+ * 1/9) for the two colours A (non-wetting) and B (wetting), streamed with
+ * halfway bounce-back and then fully relaxed to the recoloured equilibrium
+ *   A_q = w_q N_A [1 + 9/2 u.xi_q + beta N_B n.xi_q],
+ *   B_q = w_q N_B [1 + 9/2 u.xi_q - beta N_A n.xi_q],
+ * with N_A = sum A_q, N_B = sum B_q, phi = (N_A - N_B)/(N_A + N_B).
+ *
+ * Readings (where Appendix A is silent): phi at a solid neighbour or beyond a
+ * non-periodic side is phi_solid (wetting); phi beyond z = 0 or z = nz-1 of an
+ * open box is the site's own phi; inlet injects pure A: A_5 = w_5 (1 + 9/2 u_z),
+ * B_5 = 0; the outlet unknowns A_6, B_6 are the equilibrium of the site's
+ * previous-step densities with the boundary velocity:
+ *   A_6 = w_6 N_A^prev (1 - 9/2 u_z), B_6 = w_6 N_B^prev (1 - 9/2 u_z).
+ * ====================================================================== */
+
+#define Q7 7
+static const double W7[Q7] = {1.0 / 3.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                              1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0};
+
+static double MB[Q19][Q19]; /* MB[k][q]: moment k of direction q */
+static double MB_NORM2[Q19];
+static int mrt_ready = 0;
+
+static void init_mrt(void)
+{
+    if (mrt_ready) return;
+    init_tables();
+    for (int q = 0; q < Q19; ++q) {
+        const double x = CX[q], y = CY[q], z = CZ[q];
+        const double c2 = x * x + y * y + z * z;
+        MB[0][q] = 1.0;
+        MB[1][q] = 19.0 * c2 - 30.0;
+        MB[2][q] = (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+        MB[3][q] = x;
+        MB[4][q] = (5.0 * c2 - 9.0) * x;
+        MB[5][q] = y;
+        MB[6][q] = (5.0 * c2 - 9.0) * y;
+        MB[7][q] = z;
+        MB[8][q] = (5.0 * c2 - 9.0) * z;
+        MB[9][q] = 3.0 * x * x - c2;
+        MB[10][q] = (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+        MB[11][q] = y * y - z * z;
+        MB[12][q] = (3.0 * c2 - 5.0) * (y * y - z * z);
+        MB[13][q] = x * y;
+        MB[14][q] = y * z;
+        MB[15][q] = x * z;
+        MB[16][q] = (y * y - z * z) * x;
+        MB[17][q] = (z * z - x * x) * y;
+        MB[18][q] = (x * x - y * y) * z;
+    }
+    for (int k = 0; k < Q19; ++k) {
+        double s = 0.0;
+        for (int q = 0; q < Q19; ++q) s += MB[k][q] * MB[k][q];
+        MB_NORM2[k] = s;
+    }
+    mrt_ready = 1;
+}
+
+void orc_mrt_matrix(double *m19x19)
+{
+    init_mrt();
+    for (int k = 0; k < Q19; ++k)
+        for (int q = 0; q < Q19; ++q) m19x19[k * Q19 + q] = MB[k][q];
+}
+
+/* MRT collision of one site with relaxation rates S[19] and the colour
+ * stress of gradient (gx, gy, gz) (alpha = 0 or C = 0: plain MRT). */
+void orc_mrt_collide_site_rates(double *f, double rho0, const double *S, double alpha, double gx,
+                                double gy, double gz)
+{
+    init_mrt();
+    double m[Q19], meq[Q19], feq[Q19];
+    double rho, jx, jy, jz;
+    moments(f, &rho, &jx, &jy, &jz);
+    orc_equilibrium(rho, rho0, jx / rho0, jy / rho0, jz / rho0, feq);
+    for (int k = 0; k < Q19; ++k) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < Q19; ++q) {
+            a += MB[k][q] * f[q];
+            b += MB[k][q] * feq[q];
+        }
+        m[k] = a;
+        meq[k] = b;
+    }
+    const double cmag = sqrt(gx * gx + gy * gy + gz * gz);
+    if (alpha != 0.0 && cmag > 1e-6) {
+        const double nx = gx / cmag, ny = gy / cmag, nz = gz / cmag;
+        const double ac = alpha * cmag;
+        meq[1] += 19.0 * ac;
+        meq[9] += 0.5 * ac * (2.0 * nx * nx - ny * ny - nz * nz);
+        meq[11] += 0.5 * ac * (ny * ny - nz * nz);
+        meq[13] += 0.5 * ac * nx * ny;
+        meq[14] += 0.5 * ac * ny * nz;
+        meq[15] += 0.5 * ac * nx * nz;
+    }
+    for (int k = 0; k < Q19; ++k) m[k] = m[k] - S[k] * (m[k] - meq[k]);
+    for (int q = 0; q < Q19; ++q) {
+        double v = 0.0;
+        for (int k = 0; k < Q19; ++k) v += MB[k][q] * m[k] / MB_NORM2[k];
+        f[q] = v;
+    }
+}
+
+/* The paper's rates: s_e = s_eps = s_pi = s_nu = 1/tau, s_q = s_m =
+ * 8 (2 - s_nu)/(8 - s_nu); density and momentum are not relaxed. */
+void orc_mrt_collide_site(double *f, double rho0, double tau, double alpha, double gx, double gy,
+                          double gz)
+{
+    const double snu = 1.0 / tau;
+    const double sq = 8.0 * (2.0 - snu) / (8.0 - snu);
+    const double S[Q19] = {0.0, snu, snu, 0.0, sq, 0.0, sq, 0.0, sq, snu,
+                           snu, snu, snu, snu, snu, snu, sq,  sq,  sq};
+    orc_mrt_collide_site_rates(f, rho0, S, alpha, gx, gy, gz);
+}
+
+typedef struct orc_colour {
+    orc_lattice *L;
+    double alpha, beta, phi_solid;
+    double *A, *B, *At, *Bt; /* [cell][7] */
+    double *na, *nb, *phi;   /* [cell] after streaming of the step in progress */
+    double *uz_in, *uz_out;  /* [ny][nx] boundary velocities */
+} orc_colour;
+
+orc_colour *orc_colour_create(int nx, int ny, int nz, const unsigned char *solid, int periodic_x,
+                              int periodic_y, int z_mode, double tau, double rho0,
+                              double q_target, double rho_out, double alpha, double beta,
+                              double phi_solid)
+{
+    init_mrt();
+    orc_lattice *L = orc_create(nx, ny, nz, solid, periodic_x, periodic_y, z_mode, tau, rho0,
+                                q_target, rho_out);
+    if (!L) return NULL;
+    orc_colour *C = (orc_colour *)calloc(1, sizeof(orc_colour));
+    if (!C) {
+        orc_destroy(L);
+        return NULL;
+    }
+    C->L = L;
+    C->alpha = alpha;
+    C->beta = beta;
+    C->phi_solid = phi_solid;
+    size_t n7 = (size_t)L->ncell * Q7;
+    C->A = (double *)calloc(n7, sizeof(double));
+    C->B = (double *)calloc(n7, sizeof(double));
+    C->At = (double *)calloc(n7, sizeof(double));
+    C->Bt = (double *)calloc(n7, sizeof(double));
+    C->na = (double *)calloc((size_t)L->ncell, sizeof(double));
+    C->nb = (double *)calloc((size_t)L->ncell, sizeof(double));
+    C->phi = (double *)calloc((size_t)L->ncell, sizeof(double));
+    C->uz_in = (double *)calloc((size_t)nx * ny, sizeof(double));
+    C->uz_out = (double *)calloc((size_t)nx * ny, sizeof(double));
+    if (!C->A || !C->B || !C->At || !C->Bt || !C->na || !C->nb || !C->phi || !C->uz_in ||
+        !C->uz_out) {
+        /* leave cleanup to the caller's destroy */
+    }
+    return C;
+}
+
+void orc_colour_destroy(orc_colour *C)
+{
+    if (!C) return;
+    orc_destroy(C->L);
+    free(C->A);
+    free(C->B);
+    free(C->At);
+    free(C->Bt);
+    free(C->na);
+    free(C->nb);
+    free(C->phi);
+    free(C->uz_in);
+    free(C->uz_out);
+    free(C);
+}
+
+/* Rest momentum state (rho = 1, u = 0) and colour densities na, nb (dense
+ * [cell]) as D3Q7 equilibria at rest. */
+void orc_colour_init(orc_colour *C, const double *na, const double *nb)
+{
+    orc_lattice *L = C->L;
+    orc_init_equilibrium(L, 1.0, 0.0, 0.0, 0.0);
+    for (long c = 0; c < L->ncell; ++c)
+        for (int q = 0; q < Q7; ++q) {
+            C->A[c * Q7 + q] = L->solid[c] ? 0.0 : W7[q] * na[c];
+            C->B[c * Q7 + q] = L->solid[c] ? 0.0 : W7[q] * nb[c];
+        }
+}
+
+void orc_colour_set_state(orc_colour *C, const double *f, const double *A, const double *B)
+{
+    orc_lattice *L = C->L;
+    orc_set_f(L, f);
+    for (long c = 0; c < L->ncell; ++c)
+        for (int q = 0; q < Q7; ++q) {
+            C->A[c * Q7 + q] = L->solid[c] ? 0.0 : A[c * Q7 + q];
+            C->B[c * Q7 + q] = L->solid[c] ? 0.0 : B[c * Q7 + q];
+        }
+}
+
+void orc_colour_get_state(const orc_colour *C, double *f, double *A, double *B)
+{
+    orc_get_f(C->L, f);
+    memcpy(A, C->A, (size_t)C->L->ncell * Q7 * sizeof(double));
+    memcpy(B, C->B, (size_t)C->L->ncell * Q7 * sizeof(double));
+}
+
+/* phi of the neighbour x + xi_q of pore cell (x, y, z), with the readings
+ * above for solids, sides and the open z faces. */
+static double neighbour_phi(const orc_colour *C, int x, int y, int z, int q)
+{
+    const orc_lattice *L = C->L;
+    int tx = x + CX[q], ty = y + CY[q], tz = z + CZ[q];
+    if (tz < 0 || tz >= L->nz) {
+        if (L->z_mode == ORC_Z_PERIODIC)
+            tz = (tz + L->nz) % L->nz;
+        else if (L->z_mode == ORC_Z_WALL)
+            return C->phi_solid;
+        else
+            return C->phi[cell_index(L, x, y, z)];
+    }
+    if (tx < 0 || tx >= L->nx) {
+        if (!L->periodic_x) return C->phi_solid;
+        tx = (tx + L->nx) % L->nx;
+    }
+    if (ty < 0 || ty >= L->ny) {
+        if (!L->periodic_y) return C->phi_solid;
+        ty = (ty + L->ny) % L->ny;
+    }
+    long t = cell_index(L, tx, ty, tz);
+    return L->solid[t] ? C->phi_solid : C->phi[t];
+}
+
+/* One two-fluid step. hist (may be NULL): rho_in, Q_in, Q_out, mass, max|u|,
+ * sum N_A, sum N_B. */
+static int colour_step_once(orc_colour *C, double *hist)
+{
+    orc_lattice *L = C->L;
+    const int nx = L->nx, ny = L->ny, nz = L->nz;
+    const double rho0 = L->rho0;
+
+    /* previous colour densities at the outlet sites (stored state) */
+    double *na_prev = (double *)malloc((size_t)nx * ny * sizeof(double));
+    double *nb_prev = (double *)malloc((size_t)nx * ny * sizeof(double));
+    if (!na_prev || !nb_prev) {
+        free(na_prev);
+        free(nb_prev);
+        return -2;
+    }
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long c = cell_index(L, x, y, nz - 1);
+            double a = 0.0, b = 0.0;
+            for (int q = 0; q < Q7; ++q) {
+                a += C->A[c * Q7 + q];
+                b += C->B[c * Q7 + q];
+            }
+            na_prev[x + nx * y] = a;
+            nb_prev[x + nx * y] = b;
+        }
+
+    /* 1. stream f, A, B */
+    stream_push_n(L, L->f, L->ft, Q19);
+    stream_push_n(L, C->A, C->At, Q7);
+    stream_push_n(L, C->B, C->Bt, Q7);
+
+    /* 2. momentum boundary conditions (as for the single fluid) */
+    double rho_in, q_in, q_out;
+    apply_momentum_bc(L, C->uz_in, C->uz_out, &rho_in, &q_in, &q_out);
+
+    /* 3. mass-transport boundary unknowns */
+    if (L->z_mode == ORC_Z_FLUX) {
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long c = cell_index(L, x, y, 0);
+                if (L->solid[c]) continue;
+                const double uz = C->uz_in[x + nx * y];
+                C->At[c * Q7 + 5] = W7[5] * 1.0 * (1.0 + 4.5 * uz);
+                C->Bt[c * Q7 + 5] = 0.0;
+            }
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long c = cell_index(L, x, y, nz - 1);
+                if (L->solid[c]) continue;
+                const double uz = C->uz_out[x + nx * y];
+                C->At[c * Q7 + 6] = W7[6] * na_prev[x + nx * y] * (1.0 - 4.5 * uz);
+                C->Bt[c * Q7 + 6] = W7[6] * nb_prev[x + nx * y] * (1.0 - 4.5 * uz);
+            }
+    }
+    free(na_prev);
+    free(nb_prev);
+
+    int bad = any_unset(L, L->ft, Q19) | any_unset(L, C->At, Q7) | any_unset(L, C->Bt, Q7);
+
+    /* 4. phase field at every pore site */
+#pragma omp parallel for schedule(static)
+    for (long c = 0; c < L->ncell; ++c) {
+        if (L->solid[c]) continue;
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < Q7; ++q) {
+            a += C->At[c * Q7 + q];
+            b += C->Bt[c * Q7 + q];
+        }
+        C->na[c] = a;
+        C->nb[c] = b;
+        C->phi[c] = (a + b) != 0.0 ? (a - b) / (a + b) : 0.0;
+    }
+
+    double umax = hist ? max_speed(L, L->ft) : 0.0;
+
+    /* 5-7. colour gradient, MRT with the interfacial stress, recolouring */
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                long c = cell_index(L, x, y, z);
+                if (L->solid[c]) continue;
+                double gx = 0.0, gy = 0.0, gz = 0.0;
+                for (int q = 1; q < Q19; ++q) {
+                    const double p = neighbour_phi(C, x, y, z, q);
+                    gx += 3.0 * W[q] * CX[q] * p;
+                    gy += 3.0 * W[q] * CY[q] * p;
+                    gz += 3.0 * W[q] * CZ[q] * p;
+                }
+                double *f = &L->ft[c * Q19];
+                double rho, jx, jy, jz;
+                moments(f, &rho, &jx, &jy, &jz);
+                const double ux = jx / rho0, uy = jy / rho0, uz = jz / rho0;
+                if (!L->collide) continue; /* testing aid: pure streaming */
+                orc_mrt_collide_site(f, rho0, L->tau, C->alpha, gx, gy, gz);
+                const double cmag = sqrt(gx * gx + gy * gy + gz * gz);
+                double nxv = 0.0, nyv = 0.0, nzv = 0.0;
+                if (cmag > 1e-6) {
+                    nxv = gx / cmag;
+                    nyv = gy / cmag;
+                    nzv = gz / cmag;
+                }
+                const double na = C->na[c], nb = C->nb[c];
+                for (int q = 0; q < Q7; ++q) {
+                    const double cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
+                    const double cn = CX[q] * nxv + CY[q] * nyv + CZ[q] * nzv;
+                    C->At[c * Q7 + q] = W7[q] * na * (1.0 + 4.5 * cu + C->beta * nb * cn);
+                    C->Bt[c * Q7 + q] = W7[q] * nb * (1.0 + 4.5 * cu - C->beta * na * cn);
+                }
+            }
+
+    if (hist) {
+        hist[0] = rho_in;
+        hist[1] = q_in;
+        hist[2] = q_out;
+        hist[3] = total_mass(L, L->ft, Q19);
+        hist[4] = umax;
+        hist[5] = total_mass(L, C->At, Q7);
+        hist[6] = total_mass(L, C->Bt, Q7);
+    }
+    double *t = L->f;
+    L->f = L->ft;
+    L->ft = t;
+    t = C->A;
+    C->A = C->At;
+    C->At = t;
+    t = C->B;
+    C->B = C->Bt;
+    C->Bt = t;
+    L->step++;
+    return bad ? -1 : 0;
+}
+
+int orc_colour_step(orc_colour *C, int n, double *hist)
+{
+    for (int i = 0; i < n; ++i) {
+        int rc = colour_step_once(C, hist ? hist + 7 * (long)i : NULL);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+/* Dense fields of the stored state: rho, u, and phi from the stored A, B. */
+void orc_colour_fields(const orc_colour *C, double *rho, double *ux, double *uy, double *uz,
+                       double *phi)
+{
+    const orc_lattice *L = C->L;
+    orc_fields(L, rho, ux, uy, uz);
+    for (long c = 0; c < L->ncell; ++c) {
+        if (L->solid[c]) {
+            phi[c] = 0.0;
+            continue;
+        }
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < Q7; ++q) {
+            a += C->A[c * Q7 + q];
+            b += C->B[c * Q7 + q];
+        }
+        phi[c] = (a + b) != 0.0 ? (a - b) / (a + b) : 0.0;
+    }
+}
+
+void orc_colour_set_collision(orc_colour *C, int on) { C->L->collide = on; }

@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["lbm_oracle.c", "colour_oracle.c"]
+_SOURCES = ["lbm_oracle.c"]
 _lock = threading.Lock()
 _lib = None
 
@@ -74,6 +74,19 @@ def _load():
         lib.orc_inlet_bc_site.restype = _d
         lib.orc_outlet_bc_site.argtypes = [_p, _d, _d]
         lib.orc_outlet_bc_site.restype = _d
+        lib.orc_mrt_matrix.argtypes = [_p]
+        lib.orc_mrt_collide_site.argtypes = [_p, _d, _d, _d, _d, _d, _d]
+        lib.orc_mrt_collide_site_rates.argtypes = [_p, _d, _p, _d, _d, _d, _d]
+        lib.orc_colour_create.restype = _p
+        lib.orc_colour_create.argtypes = [_i, _i, _i, _p, _i, _i, _i, _d, _d, _d, _d, _d, _d, _d]
+        lib.orc_colour_destroy.argtypes = [_p]
+        lib.orc_colour_init.argtypes = [_p, _p, _p]
+        lib.orc_colour_set_state.argtypes = [_p, _p, _p, _p]
+        lib.orc_colour_get_state.argtypes = [_p, _p, _p, _p]
+        lib.orc_colour_step.argtypes = [_p, _i, _p]
+        lib.orc_colour_step.restype = _i
+        lib.orc_colour_fields.argtypes = [_p, _p, _p, _p, _p, _p]
+        lib.orc_colour_set_collision.argtypes = [_p, _i]
         _lib = lib
         return lib
 
@@ -114,6 +127,28 @@ def outlet_bc_site(f: np.ndarray, rho: float, rho0: float = 1.0):
     g = np.ascontiguousarray(f, dtype=np.float64).copy()
     uz = lib.orc_outlet_bc_site(_ptr(g), float(rho), float(rho0))
     return g, uz
+
+
+def mrt_matrix() -> np.ndarray:
+    """The 19x19 moment matrix M (rows: moments in Appendix A's order)."""
+    out = np.zeros((19, 19), np.float64)
+    _load().orc_mrt_matrix(_ptr(out))
+    return out
+
+
+def mrt_collide_site(f, tau, alpha=0.0, grad=(0.0, 0.0, 0.0), rho0=1.0) -> np.ndarray:
+    """One site's MRT collision with the colour stress of gradient `grad`."""
+    g = np.ascontiguousarray(f, dtype=np.float64).copy()
+    _load().orc_mrt_collide_site(_ptr(g), float(rho0), float(tau), float(alpha), *map(float, grad))
+    return g
+
+
+def mrt_collide_site_rates(f, rates, alpha=0.0, grad=(0.0, 0.0, 0.0), rho0=1.0) -> np.ndarray:
+    """MRT collision of one site with an explicit diagonal of 19 rates."""
+    g = np.ascontiguousarray(f, dtype=np.float64).copy()
+    r = np.ascontiguousarray(rates, dtype=np.float64)
+    _load().orc_mrt_collide_site_rates(_ptr(g), float(rho0), _ptr(r), float(alpha), *map(float, grad))
+    return g
 
 
 def set_threads(n: int) -> None:
@@ -200,4 +235,68 @@ class OracleLattice:
         rc = self._lib.orc_step(self._h, int(n), _ptr(hist) if record else None)
         if rc != 0:
             raise RuntimeError("oracle: a population slot was left unset by streaming")
+        return hist
+
+
+class OracleColour:
+    """Dense FP64 two-fluid colour-gradient lattice (Appendix A) with the flux
+    inlet and pressure outlet. State: f (nz,ny,nx,19), A and B (nz,ny,nx,7)."""
+
+    HIST_FIELDS = ("rho_in", "q_in", "q_out", "mass", "umax", "sum_na", "sum_nb")
+
+    def __init__(self, mask: np.ndarray, *, tau: float, alpha: float, beta: float,
+                 phi_solid: float, q_target: float = 0.0, rho_out: float = 1.0,
+                 rho0: float = 1.0, periodic_x: bool = False, periodic_y: bool = False,
+                 z_mode: int = Z_FLUX):
+        lib = _load()
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        self.shape = mask.shape
+        self.mask = mask
+        nz, ny, nx = mask.shape
+        h = lib.orc_colour_create(nx, ny, nz, _ptr(mask), int(periodic_x), int(periodic_y),
+                                  int(z_mode), float(tau), float(rho0), float(q_target),
+                                  float(rho_out), float(alpha), float(beta), float(phi_solid))
+        if not h:
+            raise ValueError("oracle rejected the lattice")
+        self._h = h
+        self._lib = lib
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_colour_destroy(h)
+            self._h = None
+
+    def set_collision(self, on: bool) -> None:
+        self._lib.orc_colour_set_collision(self._h, int(bool(on)))
+
+    def init(self, na: np.ndarray, nb: np.ndarray) -> None:
+        na = np.ascontiguousarray(na, dtype=np.float64)
+        nb = np.ascontiguousarray(nb, dtype=np.float64)
+        self._lib.orc_colour_init(self._h, _ptr(na), _ptr(nb))
+
+    def set_state(self, f, A, B) -> None:
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        B = np.ascontiguousarray(B, dtype=np.float64)
+        self._lib.orc_colour_set_state(self._h, _ptr(f), _ptr(A), _ptr(B))
+
+    def get_state(self):
+        f = np.empty(self.shape + (19,), np.float64)
+        A = np.empty(self.shape + (7,), np.float64)
+        B = np.empty(self.shape + (7,), np.float64)
+        self._lib.orc_colour_get_state(self._h, _ptr(f), _ptr(A), _ptr(B))
+        return f, A, B
+
+    def fields(self):
+        """(rho, ux, uy, uz, phi) dense arrays of the stored state."""
+        arrs = [np.empty(self.shape, np.float64) for _ in range(5)]
+        self._lib.orc_colour_fields(self._h, *[_ptr(a) for a in arrs])
+        return tuple(arrs)
+
+    def step(self, n: int = 1, record: bool = True):
+        hist = np.empty((n, 7), np.float64) if record else None
+        rc = self._lib.orc_colour_step(self._h, int(n), _ptr(hist) if record else None)
+        if rc != 0:
+            raise RuntimeError(f"colour oracle step failed ({rc})")
         return hist

@@ -128,7 +128,8 @@ def test_pull_table_matches_definition(z_mode, px, py):
     nz, ny, nx = mask.shape
     assert np.array_equal(coords[:, 0] + nx * (coords[:, 1] + ny * coords[:, 2]), sites)
     nbr = fluxlbm.flbm_get_pull_table(ctx, n)
-    npad = (n + 255) // 256 * 256
+    _, _, npad = fluxlbm.flbm_device_layout(ctx)
+    assert npad % 1024 == 0 and npad >= n
     assert np.array_equal(nbr, _brute_pull(mask, px, py, z_mode, npad))
     fluxlbm.flbm_destroy(ctx)
 
