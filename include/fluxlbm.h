@@ -207,11 +207,13 @@ flbm_status flbm_get_observables(flbm_ctx *c, double *mass, double *umax, int32_
  * [18][n_pad]); for profiling and zero-copy inspection. */
 flbm_status flbm_device_layout(const flbm_ctx *c, void **f_cur, void **nbr, int64_t *n_pad);
 
-/* Profiling: run n steps launched one by one (no graph, no watchdog
- * reduction), each kernel bracketed by HIP events on the context's stream,
- * and return the mean duration in milliseconds of the inlet-plane reduction
- * and of the fused stream-collide kernel. The steps are real steps (the
- * state advances). Synchronises. */
+/* Profiling: recompute the inlet consistency sum from the state with the
+ * inlet-plane reduction kernel, then run n steps launched one by one (no
+ * graph, no watchdog reduction), each kernel bracketed by HIP events on the
+ * context's stream; return the duration in milliseconds of the plane
+ * reduction and the mean duration of the fused stream-collide kernel. (In a
+ * run of steps the plane reduction runs only once: each step kernel carries
+ * the next step's inlet sum.) The steps are real steps. Synchronises. */
 flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, double *ms_step);
 
 /* Stream-copy calibration kernel: copies `bytes` (a multiple of 16, both

@@ -46,7 +46,11 @@ struct flbm_ctx {
     std::string err;
 
     // launch geometry
-    int tiles = 0, nt_in = 0, tout0 = 0, n_bnd = 0, plane_blocks = 0;
+    int tiles = 0, nt_in = 0, nt01 = 0, tout0 = 0, n_bnd = 0, plane_blocks = 0;
+    int blocks256 = 0;  // n_pad / BLOCK: grid of the one-site-per-thread kernels
+    bool use_buf = false; // f and nbr each below 4 GiB: buffer-instruction path
+    bool need_plane = true; // the carried inlet sum is stale (state set from the host)
+    int obs_slots = 0;  // per-tile observable partials: max(tiles, blocks256)
     size_t elem = 4;  // bytes per stored population
 
     // device memory
@@ -57,7 +61,8 @@ struct flbm_ctx {
     int cur = 0;
     int32_t *nbr = nullptr;
     DevState *st = nullptr;
-    double *kpart = nullptr, *bpart_in = nullptr, *bpart_out = nullptr;
+    double *kpart = nullptr, *bpart_in = nullptr, *bpart_out = nullptr, *spart = nullptr;
+    uint64_t *kcoef = nullptr;
     double *obs_mass = nullptr;
     float *obs_umax2 = nullptr;
     uint32_t *obs_bad = nullptr;
@@ -108,9 +113,11 @@ size_t carve(flbm_ctx *c, char *base)
     char *kp = take(PLANE_MAX_BLOCKS * sizeof(double));
     char *bi = take((size_t)std::max(1, c->nt_in) * sizeof(double));
     char *bo = take((size_t)std::max(1, c->tiles - c->tout0) * sizeof(double));
-    char *om = take((size_t)c->tiles * sizeof(double));
-    char *ou = take((size_t)c->tiles * sizeof(float));
-    char *ob = take((size_t)c->tiles * sizeof(uint32_t));
+    char *sp = take((size_t)std::max(1, c->nt01) * sizeof(double));
+    char *kc = take((size_t)std::max<int64_t>(1, (int64_t)c->lat.kcoef.size()) * sizeof(uint64_t));
+    char *om = take((size_t)c->obs_slots * sizeof(double));
+    char *ou = take((size_t)c->obs_slots * sizeof(float));
+    char *ob = take((size_t)c->obs_slots * sizeof(uint32_t));
     char *hi = take((size_t)HIST_CAP * HIST_STRIDE * sizeof(double));
     char *fl = take((size_t)4 * npad * sizeof(double));
     if (base) {
@@ -121,6 +128,8 @@ size_t carve(flbm_ctx *c, char *base)
         c->kpart = (double *)kp;
         c->bpart_in = (double *)bi;
         c->bpart_out = (double *)bo;
+        c->spart = (double *)sp;
+        c->kcoef = (uint64_t *)kc;
         c->obs_mass = (double *)om;
         c->obs_umax2 = (float *)ou;
         c->obs_bad = (uint32_t *)ob;
@@ -135,10 +144,16 @@ StepArgs step_args(const flbm_ctx *c)
     StepArgs a{};
     a.n = c->lat.n;
     a.npad = c->lat.n_pad;
+    a.f_bytes = c->use_buf ? (uint32_t)f_bytes(c) : 0u;
+    a.nbr_bytes = c->use_buf ? (uint32_t)((uint64_t)18 * c->lat.n_pad * 4) : 0u;
     const bool flux = c->p.z_mode == FLBM_Z_FLUX;
     a.a_in = flux ? c->lat.a_in : 0;
     a.out0 = flux ? c->lat.n - c->lat.a_out : c->lat.n;
+    a.n01 = flux ? c->lat.n01 : 0;
     a.nt_in = flux ? c->nt_in : 0;
+    a.nt01 = flux ? c->nt01 : 0;
+    a.kcoef = c->kcoef;
+    a.spart = c->spart;
     a.tout0 = flux ? c->tout0 : c->tiles;
     a.n_bnd = c->n_bnd;
     a.hist_cap = HIST_CAP;
@@ -155,24 +170,22 @@ StepArgs step_args(const flbm_ctx *c)
     return a;
 }
 
-PlaneArgs plane_args(const flbm_ctx *c)
+PlaneArgs plane_args(const flbm_ctx *c, int slot)
 {
     PlaneArgs a{};
     a.npad = c->lat.n_pad;
     a.a_in = c->lat.a_in;
-    a.hist_cap = HIST_CAP;
-    a.rho0 = c->p.rho0;
+    a.slot = slot;
     a.st = c->st;
     a.kpart = c->kpart;
-    a.hist = c->hist;
     return a;
 }
 
-ObsArgs obs_args(const flbm_ctx *c, int to_history)
+ObsArgs obs_args(const flbm_ctx *c, int to_history, int partials)
 {
     ObsArgs a{};
     a.n = c->lat.n;
-    a.tiles = c->tiles;
+    a.tiles = partials;
     a.hist_cap = HIST_CAP;
     a.umax_limit = c->p.umax_limit;
     a.to_history = to_history;
@@ -185,23 +198,35 @@ ObsArgs obs_args(const flbm_ctx *c, int to_history)
     return a;
 }
 
+// The fused kernel in its four variants: with or without the watchdog
+// partials; buffer instructions (buffers below 4 GiB) or 64-bit addressing.
+template <typename T>
+void launch_stream_collide(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bool obs)
+{
+    StepArgs a = step_args(c);
+    a.rd = fin == (const T *)c->f[1] ? 1 : 0;
+    const dim3 grid(c->tiles), block(SC_BLOCK);
+    if (c->use_buf) {
+        if (obs)
+            hipLaunchKernelGGL((k_stream_collide<T, true, true>), grid, block, 0, s, fin, fout, c->nbr, a);
+        else
+            hipLaunchKernelGGL((k_stream_collide<T, false, true>), grid, block, 0, s, fin, fout, c->nbr, a);
+    } else {
+        if (obs)
+            hipLaunchKernelGGL((k_stream_collide<T, true, false>), grid, block, 0, s, fin, fout, c->nbr, a);
+        else
+            hipLaunchKernelGGL((k_stream_collide<T, false, false>), grid, block, 0, s, fin, fout, c->nbr, a);
+    }
+}
+
 // Enqueue one step from buffer `from` on stream s.
 template <typename T>
 void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
 {
     const T *fin = (const T *)c->f[from];
     T *fout = (T *)c->f[from ^ 1];
-    if (c->p.z_mode == FLBM_Z_FLUX)
-        hipLaunchKernelGGL(k_inlet_plane<T>, dim3(c->plane_blocks), dim3(BLOCK), 0, s, fin, c->nbr,
-                           plane_args(c));
-    if (obs) {
-        hipLaunchKernelGGL((k_stream_collide<T, true>), dim3(c->tiles), dim3(BLOCK), 0, s, fin, fout,
-                           c->nbr, step_args(c));
-        hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1));
-    } else {
-        hipLaunchKernelGGL((k_stream_collide<T, false>), dim3(c->tiles), dim3(BLOCK), 0, s, fin,
-                           fout, c->nbr, step_args(c));
-    }
+    launch_stream_collide<T>(c, s, fin, fout, obs);
+    if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
 }
 
 void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
@@ -238,18 +263,34 @@ flbm_status capture_graph(flbm_ctx *c, int parity)
     return FLBM_OK;
 }
 
+// The step kernel carries the inlet consistency sum from one step to the
+// next; when the state was set from the host, recompute it from the state.
+flbm_status refresh_inlet_sum(flbm_ctx *c)
+{
+    if (!c->need_plane || c->p.z_mode != FLBM_Z_FLUX) return FLBM_OK;
+    if (is_fp64(c))
+        hipLaunchKernelGGL(k_inlet_plane<double>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
+                           (const double *)c->f[c->cur], c->nbr, plane_args(c, c->cur));
+    else
+        hipLaunchKernelGGL(k_inlet_plane<float>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
+                           (const float *)c->f[c->cur], c->nbr, plane_args(c, c->cur));
+    HIPCHK(c, hipGetLastError());
+    c->need_plane = false;
+    return FLBM_OK;
+}
+
 flbm_status reset_state(flbm_ctx *c)
 {
     DevState h{};
     h.q_target = c->p.q_target;
     h.drho_out = c->p.rho_out - 1.0;
-    h.drho_in = 0.0;
     h.omega = c->collide ? 1.0 / c->p.tau : 0.0;
     h.step = 0;
     HIPCHK(c, hipMemcpyAsync(c->st, &h, sizeof(h), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->hist, 0xff, (size_t)HIST_CAP * HIST_STRIDE * sizeof(double), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->steps = 0;
+    c->need_plane = true;
     return FLBM_OK;
 }
 
@@ -287,6 +328,9 @@ flbm_status setup_device(flbm_ctx *c, void *mem)
     carve(c, (char *)mem);
     HIPCHK(c, hipMemcpyAsync(c->nbr, c->lat.nbr.data(), c->lat.nbr.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
+    if (!c->lat.kcoef.empty())
+        HIPCHK(c, hipMemcpyAsync(c->kcoef, c->lat.kcoef.data(), c->lat.kcoef.size() * sizeof(uint64_t),
+                                 hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->kpart, 0, PLANE_MAX_BLOCKS * sizeof(double), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->ready = true;
@@ -378,13 +422,18 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
         delete c;
         return FLBM_EINVAL;
     }
-    c->tiles = (int)(c->lat.n_pad / BLOCK);
+    c->tiles = (int)(c->lat.n_pad / TILE);
+    c->use_buf = f_bytes(c) < (1ull << 32) && (uint64_t)18 * c->lat.n_pad * 4 < (1ull << 32);
+    c->blocks256 = (int)(c->lat.n_pad / BLOCK);
+    c->obs_slots = std::max(c->tiles, c->blocks256);
     const bool flux = p->z_mode == FLBM_Z_FLUX;
-    c->nt_in = flux ? (int)((c->lat.a_in + BLOCK - 1) / BLOCK) : 0;
-    c->tout0 = flux ? (int)((c->lat.n - c->lat.a_out) / BLOCK) : c->tiles;
+    c->nt_in = flux ? (int)((c->lat.a_in + TILE - 1) / TILE) : 0;
+    c->nt01 = flux ? (int)((c->lat.n01 + TILE - 1) / TILE) : 0;
+    c->tout0 = flux ? (int)((c->lat.n - c->lat.a_out) / TILE) : c->tiles;
     if (flux) {
-        const int overlap = std::max(0, c->nt_in - c->tout0);
-        c->n_bnd = c->nt_in + (c->tiles - c->tout0) - overlap;
+        // boundary tiles: [0, nt01) (planes 0-1, including the inlet) and [tout0, tiles)
+        const int overlap = std::max(0, c->nt01 - c->tout0);
+        c->n_bnd = c->nt01 + (c->tiles - c->tout0) - overlap;
     } else {
         c->n_bnd = 1;
     }
@@ -459,20 +508,31 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr)
 flbm_status flbm_state_bytes(const flbm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return FLBM_EINVAL;
-    *bytes = (size_t)19 * c->lat.n_pad * c->elem + sizeof(int64_t);
+    *bytes = (size_t)19 * c->lat.n_pad * c->elem + 3 * sizeof(int64_t);
     return FLBM_OK;
 }
+
+// Checkpoint trailer after the distributions: step count, a flag telling
+// whether the carried inlet sum is valid, and that sum.
+struct StateTrailer {
+    int64_t steps;
+    int64_t carry_valid;
+    double s_carry;
+};
 
 flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes)
 {
     if (!c || !host) return FLBM_EINVAL;
     const size_t fb = (size_t)19 * c->lat.n_pad * c->elem;
-    if (bytes < fb + sizeof(int64_t)) return fail(c, FLBM_EBOUND, "host buffer too small");
+    if (bytes < fb + sizeof(StateTrailer)) return fail(c, FLBM_EBOUND, "host buffer too small");
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(host, c->f[c->cur], fb, hipMemcpyDeviceToHost));
-    std::memcpy((char *)host + fb, &c->steps, sizeof(int64_t));
+    DevState d{};
+    HIPCHK(c, hipMemcpy(&d, c->st, sizeof(d), hipMemcpyDeviceToHost));
+    StateTrailer tr{c->steps, c->need_plane ? 0 : 1, d.s_carry[c->cur]};
+    std::memcpy((char *)host + fb, &tr, sizeof(tr));
     return FLBM_OK;
 }
 
@@ -480,18 +540,23 @@ flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
 {
     if (!c || !host) return FLBM_EINVAL;
     const size_t fb = (size_t)19 * c->lat.n_pad * c->elem;
-    if (bytes < fb + sizeof(int64_t)) return fail(c, FLBM_EBOUND, "host buffer too small");
+    if (bytes < fb + sizeof(StateTrailer)) return fail(c, FLBM_EBOUND, "host buffer too small");
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->f[c->cur], host, fb, hipMemcpyHostToDevice));
     rc = reset_state(c);
     if (rc) return rc;
-    int64_t steps = 0;
-    std::memcpy(&steps, (const char *)host + fb, sizeof(int64_t));
-    // Restore the step counter on both sides so history slots line up.
-    c->steps = steps;
-    HIPCHK(c, hipMemcpy(&c->st->step, &steps, sizeof(int64_t), hipMemcpyHostToDevice));
+    StateTrailer tr{};
+    std::memcpy(&tr, (const char *)host + fb, sizeof(tr));
+    // Restore the step counter on both sides so history slots line up, and
+    // the carried inlet sum so the resumed run is bitwise the same.
+    c->steps = tr.steps;
+    HIPCHK(c, hipMemcpy(&c->st->step, &tr.steps, sizeof(int64_t), hipMemcpyHostToDevice));
+    if (tr.carry_valid) {
+        HIPCHK(c, hipMemcpy(&c->st->s_carry[c->cur], &tr.s_carry, sizeof(double), hipMemcpyHostToDevice));
+        c->need_plane = false;
+    }
     return FLBM_OK;
 }
 
@@ -542,6 +607,10 @@ flbm_status flbm_step(flbm_ctx *c, int32_t n)
     if (!c || n < 0) return FLBM_EINVAL;
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
+    if (n > 0) {
+        rc = refresh_inlet_sum(c);
+        if (rc) return rc;
+    }
     int32_t left = n;
     while (left > 0) {
         if (c->use_graph && left >= c->chunk) {
@@ -635,10 +704,10 @@ flbm_status flbm_read_fields(flbm_ctx *c, double *rho, double *ux, double *uy, d
     if (rc) return rc;
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
     if (is_fp64(c))
-        hipLaunchKernelGGL(k_moments<double>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+        hipLaunchKernelGGL(k_moments<double>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
                            (const double *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
     else
-        hipLaunchKernelGGL(k_moments<float>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+        hipLaunchKernelGGL(k_moments<float>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
                            (const float *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -696,14 +765,14 @@ flbm_status flbm_get_observables(flbm_ctx *c, double *mass, double *umax, int32_
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     if (is_fp64(c))
-        hipLaunchKernelGGL(k_state_observables<double>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+        hipLaunchKernelGGL(k_state_observables<double>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
                            (const double *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
                            c->obs_umax2, c->obs_bad);
     else
-        hipLaunchKernelGGL(k_state_observables<float>, dim3(c->tiles), dim3(BLOCK), 0, c->stream,
+        hipLaunchKernelGGL(k_state_observables<float>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
                            (const float *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
                            c->obs_umax2, c->obs_bad);
-    hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, c->stream, obs_args(c, 0));
+    hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, c->stream, obs_args(c, 0, c->blocks256));
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     DevState h{};
@@ -728,41 +797,37 @@ flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, doubl
     if (!c || n < 1) return FLBM_EINVAL;
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
-    hipEvent_t ev[3];
+    hipEvent_t ev[2];
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     double tp = 0.0, ts = 0.0;
-    const bool flux = c->p.z_mode == FLBM_Z_FLUX;
+    float ms = 0.f;
+    if (c->p.z_mode == FLBM_Z_FLUX) {
+        c->need_plane = true;
+        HIPCHK(c, hipEventRecord(ev[0], c->stream));
+        rc = refresh_inlet_sum(c);
+        if (rc) return rc;
+        HIPCHK(c, hipEventRecord(ev[1], c->stream));
+        HIPCHK(c, hipEventSynchronize(ev[1]));
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+        tp = ms;
+    }
     for (int32_t i = 0; i < n; ++i) {
         const int from = c->cur;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
-        if (flux) {
-            if (is_fp64(c))
-                hipLaunchKernelGGL(k_inlet_plane<double>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
-                                   (const double *)c->f[from], c->nbr, plane_args(c));
-            else
-                hipLaunchKernelGGL(k_inlet_plane<float>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
-                                   (const float *)c->f[from], c->nbr, plane_args(c));
-        }
-        HIPCHK(c, hipEventRecord(ev[1], c->stream));
         if (is_fp64(c))
-            hipLaunchKernelGGL((k_stream_collide<double, false>), dim3(c->tiles), dim3(BLOCK), 0, c->stream,
-                               (const double *)c->f[from], (double *)c->f[from ^ 1], c->nbr, step_args(c));
+            launch_stream_collide<double>(c, c->stream, (const double *)c->f[from], (double *)c->f[from ^ 1], false);
         else
-            hipLaunchKernelGGL((k_stream_collide<float, false>), dim3(c->tiles), dim3(BLOCK), 0, c->stream,
-                               (const float *)c->f[from], (float *)c->f[from ^ 1], c->nbr, step_args(c));
-        HIPCHK(c, hipEventRecord(ev[2], c->stream));
+            launch_stream_collide<float>(c, c->stream, (const float *)c->f[from], (float *)c->f[from ^ 1], false);
+        HIPCHK(c, hipEventRecord(ev[1], c->stream));
         HIPCHK(c, hipGetLastError());
-        HIPCHK(c, hipEventSynchronize(ev[2]));
-        float a = 0.f, b = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&a, ev[0], ev[1]));
-        HIPCHK(c, hipEventElapsedTime(&b, ev[1], ev[2]));
-        tp += a;
-        ts += b;
+        HIPCHK(c, hipEventSynchronize(ev[1]));
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
+        ts += ms;
         c->cur ^= 1;
         c->steps += 1;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
-    if (ms_plane) *ms_plane = tp / n;
+    if (ms_plane) *ms_plane = tp;
     if (ms_step) *ms_step = ts / n;
     return FLBM_OK;
 }
@@ -773,8 +838,9 @@ flbm_status flbm_copy_kernel(const void *src, void *dst, size_t bytes, void *hip
     if ((((uintptr_t)src) & 15) || (((uintptr_t)dst) & 15)) return FLBM_EINVAL;
     const int64_t n16 = (int64_t)(bytes / 16);
     if (n16 == 0) return FLBM_OK;
-    const int blocks = (int)std::min<int64_t>((n16 + BLOCK - 1) / BLOCK, 256 * 64);
-    hipLaunchKernelGGL(k_copy16, dim3(blocks), dim3(BLOCK), 0, (hipStream_t)hip_stream,
+    const int64_t blocks = (n16 + BLOCK - 1) / BLOCK;
+    if (blocks > INT32_MAX) return FLBM_EINVAL;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)hip_stream,
                        (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError() == hipSuccess ? FLBM_OK : FLBM_EHIP;
 }

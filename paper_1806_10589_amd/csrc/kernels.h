@@ -15,9 +15,31 @@
 
 namespace flbm {
 
-constexpr int BLOCK = 256;       // sites per block of the step kernel (4 waves)
+// Launch shape of the fused step kernel: SC_BLOCK threads, SC_V consecutive
+// sites per thread (vector loads of the pull indices and the rest
+// population, vector stores), TILE sites per block.
+#ifndef FLBM_SC_BLOCK
+#define FLBM_SC_BLOCK 512
+#endif
+#ifndef FLBM_SC_V
+#define FLBM_SC_V 1
+#endif
+#ifndef FLBM_SC_NT
+#define FLBM_SC_NT 1
+#endif
+constexpr int SC_BLOCK = FLBM_SC_BLOCK;
+constexpr bool SC_NT = FLBM_SC_NT;  // non-temporal stores of the new state
+#ifndef FLBM_SC_IDX_NT
+#define FLBM_SC_IDX_NT 1
+#endif
+constexpr int SC_IDX_AUX = FLBM_SC_IDX_NT ? 2 : 0;  // cache policy of the pull-index loads
+constexpr int SC_V = FLBM_SC_V;
+constexpr int TILE = SC_BLOCK * SC_V;
+constexpr int PAD_SITES = 1024;  // n_pad is a multiple of this (>= every TILE used)
+static_assert(PAD_SITES % TILE == 0, "tile must divide the site padding");
+
+constexpr int BLOCK = 256;       // threads per block of the other kernels
 constexpr int HIST_STRIDE = 8;   // doubles per history record
-constexpr int NUM_XCD = 8;       // MI355X: 8 XCDs, blocks dealt round-robin
 constexpr int PLANE_MAX_BLOCKS = 1024;
 
 // FP64 scalars shared by the kernels of a step. Written by single threads
@@ -25,7 +47,8 @@ constexpr int PLANE_MAX_BLOCKS = 1024;
 struct DevState {
     double q_target;      // Q*
     double drho_out;      // rho_out - 1
-    double drho_in;       // rho_in - 1 of the step in progress
+    double s_carry[2];    // inlet consistency sum (deviation form) for the next step,
+                          // slot = index of the buffer that step reads
     double omega;         // 1/tau (0 turns collision off)
     double obs_mass;      // on-demand observables
     double obs_umax;
@@ -38,16 +61,23 @@ struct DevState {
 
 struct StepArgs {
     int64_t n, npad;
+    uint32_t f_bytes, nbr_bytes;  // buffer sizes for the descriptors (BUF path)
     int64_t a_in;         // inlet sites [0, a_in)
     int64_t out0;         // outlet sites [out0, n)
+    int64_t n01;          // sites of planes z = 0 and 1: they feed the next inlet sum
     int32_t nt_in;        // tiles holding inlet sites: [0, nt_in)
+    int32_t nt01;         // tiles holding planes 0 and 1: [0, nt01)
     int32_t tout0;        // tiles holding outlet sites: [tout0, tiles)
     int32_t n_bnd;        // tiles taking part in the boundary ticket
     int32_t hist_cap;
     int32_t flux_mode;
+    int32_t rd;           // s_carry slot this step reads (its input buffer)
     int32_t pad_;
     double rho0, inv_rho0;
     DevState *st;
+    const uint64_t *kcoef;          // per site of planes 0-1: 2-bit weight of each post-collision
+                                    // population in the next step's inlet sum
+    double *spart;                  // per-tile partial of that sum
     double *bpart_in, *bpart_out;   // per-tile sums of u_z
     double *obs_mass;               // per-tile sums of rho - 1
     float *obs_umax2;               // per-tile max |u|^2
@@ -57,26 +87,148 @@ struct StepArgs {
 
 struct PlaneArgs {
     int64_t npad, a_in;
-    int32_t hist_cap;
+    int32_t slot;         // s_carry slot to fill
     int32_t pad_;
-    double rho0;
     DevState *st;
     double *kpart;
-    double *hist;
 };
 
 template <typename T> struct Compute;
 template <> struct Compute<float> { using type = float; };
 template <> struct Compute<double> { using type = double; };
 
-// Block index -> tile: the hardware deals consecutive blocks round-robin to
-// the 8 XCDs; this map gives each XCD one contiguous run of tiles, so the
-// cache lines that neighbouring tiles share stay in one XCD's L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb)
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int V> struct Vec;
+template <typename T> struct Vec<T, 1> { typedef T type; };
+template <typename T> struct Vec<T, 2> { typedef T type __attribute__((ext_vector_type(2))); };
+template <typename T> struct Vec<T, 4> { typedef T type __attribute__((ext_vector_type(4))); };
+
+
+// Buffer-resource access (CDNA raw buffer instructions): the base address
+// and byte size live in an SGPR descriptor, each lane supplies a 32-bit byte
+// offset, and a uniform row offset goes in the scalar offset field. No
+// per-lane 64-bit address arithmetic, and the hardware drops accesses beyond
+// the size. Used when every buffer of the step is below 4 GiB (checked on the
+// host); otherwise the kernel falls back to plain 64-bit global addressing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes)
 {
-    const int q = nb / NUM_XCD, r = nb % NUM_XCD;
-    const int x = b % NUM_XCD, k = b / NUM_XCD;
-    return x * q + (x < r ? x : r) + k;
+    // third descriptor word 0x00020000: raw (untyped) 32-bit data format, gfx9 family
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int BYTES> struct RawBits;
+template <> struct RawBits<4> { typedef uint32_t type; };
+template <> struct RawBits<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <> struct RawBits<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+
+template <int BYTES, int AUX = 0>
+__device__ __forceinline__ typename RawBits<BYTES>::type buf_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                                      uint32_t soff)
+{
+    if constexpr (BYTES == 4)
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX);
+    else if constexpr (BYTES == 8)
+        return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX);
+    else
+        return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, AUX);
+}
+
+// aux = 2: non-temporal (gfx940-family cache policy bit "nt")
+template <int BYTES>
+__device__ __forceinline__ void buf_store_raw_nt(typename RawBits<BYTES>::type v, __amdgpu_buffer_rsrc_t r,
+                                                 uint32_t voff, uint32_t soff)
+{
+    constexpr int aux = SC_NT ? 2 : 0;
+    if constexpr (BYTES == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, aux);
+    else if constexpr (BYTES == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, aux);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)voff, (int)soff, aux);
+}
+
+// V consecutive elements of type T at byte offset voff + soff (one load of
+// up to 16 bytes, two when V * sizeof(T) is 32).
+template <int V, typename T, typename R, int AUX = 0>
+__device__ __forceinline__ void buf_load_v(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, R (&o)[V])
+{
+    constexpr int BYTES = V * (int)sizeof(T);
+    if constexpr (BYTES > 16) {
+        R lo[V / 2], hi[V / 2];
+        buf_load_v<V / 2, T, R, AUX>(r, voff, soff, lo);
+        buf_load_v<V / 2, T, R, AUX>(r, voff + (uint32_t)(BYTES / 2), soff, hi);
+#pragma unroll
+        for (int v = 0; v < V / 2; ++v) {
+            o[v] = lo[v];
+            o[v + V / 2] = hi[v];
+        }
+    } else {
+        typedef typename Vec<T, V>::type VT;
+        const VT x = __builtin_bit_cast(VT, buf_load_raw<BYTES, AUX>(r, voff, soff));
+        if constexpr (V == 1) {
+            o[0] = (R)x;
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) o[v] = (R)x[v];
+        }
+    }
+}
+
+template <int V, typename T, typename R>
+__device__ __forceinline__ void buf_store_v_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                               const R (&val)[V])
+{
+    constexpr int BYTES = V * (int)sizeof(T);
+    if constexpr (BYTES > 16) {
+        R lo[V / 2], hi[V / 2];
+#pragma unroll
+        for (int v = 0; v < V / 2; ++v) {
+            lo[v] = val[v];
+            hi[v] = val[v + V / 2];
+        }
+        buf_store_v_nt<V / 2, T>(r, voff, soff, lo);
+        buf_store_v_nt<V / 2, T>(r, voff + (uint32_t)(BYTES / 2), soff, hi);
+    } else {
+        typedef typename Vec<T, V>::type VT;
+        VT x;
+        if constexpr (V == 1) {
+            x = (T)val[0];
+        } else {
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = (T)val[v];
+        }
+        buf_store_raw_nt<BYTES>(__builtin_bit_cast(typename RawBits<BYTES>::type, x), r, voff, soff);
+    }
+}
+
+// Load V consecutive elements (one vector load when V > 1; p is aligned to
+// V elements because site tiles start at multiples of V).
+template <int V, typename T, typename R>
+__device__ __forceinline__ void load_v(const T *__restrict__ p, R (&o)[V])
+{
+    if constexpr (V == 1) {
+        o[0] = (R)p[0];
+    } else {
+        const typename Vec<T, V>::type x = *(const typename Vec<T, V>::type *)p;
+#pragma unroll
+        for (int v = 0; v < V; ++v) o[v] = (R)x[v];
+    }
+}
+
+// Non-temporal store of V consecutive elements.
+template <int V, typename T, typename R>
+__device__ __forceinline__ void store_v_nt(T *__restrict__ p, const R (&val)[V])
+{
+    if constexpr (V == 1) {
+        __builtin_nontemporal_store((T)val[0], p);
+    } else {
+        typename Vec<T, V>::type x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = (T)val[v];
+        __builtin_nontemporal_store(x, (typename Vec<T, V>::type *)p);
+    }
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -169,42 +321,61 @@ __device__ __forceinline__ double outlet_condition(R (&g)[19], double drho_out, 
 
 // BGK relaxation toward the incompressible equilibrium
 //   f_eq = w_q [rho + rho0 (3 xi.u + 9/2 (xi.u)^2 - 3/2 u.u)],  u = j/rho0,
-// written for deviations: g_eq = w_q [(rho - 1) + rho0 (...)].
+// written for deviations: g_eq = w_q [(rho - 1) + rho0 (...)], and
+//   g <- g + omega (g_eq - g) = (1 - omega) g + omega g_eq.
+// Opposite directions share xi.u up to sign, so each pair (q, opp q) forms
+// the even part omega w (base + rho0 9/2 (xi.u)^2) once and adds / subtracts
+// the odd part omega w rho0 3 xi.u; omega and the weights are folded into
+// per-class coefficients.
 // On return g holds the post-collision deviations; drho, u the moments.
 template <typename R>
 __device__ __forceinline__ void bgk_collide(R (&g)[19], R omega, R rho0, R inv_rho0, R &drho,
                                             R &ux, R &uy, R &uz)
 {
-    R d = 0, jx = 0, jy = 0, jz = 0;
+    R d = g[0];
+    R jx = 0, jy = 0, jz = 0;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
-        d += g[q];
-        if (d3q19::cx[q]) jx += d3q19::cx[q] > 0 ? g[q] : -g[q];
-        if (d3q19::cy[q]) jy += d3q19::cy[q] > 0 ? g[q] : -g[q];
-        if (d3q19::cz[q]) jz += d3q19::cz[q] > 0 ? g[q] : -g[q];
+    for (int q = 1; q < 19; q += 2) {
+        const R sum = g[q] + g[q + 1], dif = g[q] - g[q + 1];
+        d += sum;
+        if (d3q19::cx[q]) jx += d3q19::cx[q] > 0 ? dif : -dif;
+        if (d3q19::cy[q]) jy += d3q19::cy[q] > 0 ? dif : -dif;
+        if (d3q19::cz[q]) jz += d3q19::cz[q] > 0 ? dif : -dif;
     }
     ux = jx * inv_rho0;
     uy = jy * inv_rho0;
     uz = jz * inv_rho0;
     drho = d;
+    const R keep = (R)1 - omega;
     const R base = d - rho0 * (R)1.5 * (ux * ux + uy * uy + uz * uz);
+    // omega * w * base for the three weight classes, omega * w * rho0 * {9/2, 3}
+    const R ob0 = omega * (R)(1.0 / 3.0) * base;
+    const R ob1 = omega * (R)(1.0 / 18.0) * base, ob2 = omega * (R)(1.0 / 36.0) * base;
+    const R oe1 = omega * rho0 * (R)(4.5 / 18.0), oe2 = omega * rho0 * (R)(4.5 / 36.0);
+    const R oo1 = omega * rho0 * (R)(3.0 / 18.0), oo2 = omega * rho0 * (R)(3.0 / 36.0);
+    g[0] = keep * g[0] + ob0;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) {
+    for (int q = 1; q < 19; q += 2) {  // q has positive orientation, q + 1 = opp(q)
         R cu = 0;
         if (d3q19::cx[q]) cu += d3q19::cx[q] > 0 ? ux : -ux;
         if (d3q19::cy[q]) cu += d3q19::cy[q] > 0 ? uy : -uy;
         if (d3q19::cz[q]) cu += d3q19::cz[q] > 0 ? uz : -uz;
-        const R geq = (R)d3q19::weight(q) * (base + rho0 * cu * ((R)3 + (R)4.5 * cu));
-        g[q] += omega * (geq - g[q]);
+        const bool axis = q <= 6;
+        const R even = (axis ? oe1 : oe2) * cu * cu + (axis ? ob1 : ob2);
+        const R odd = (axis ? oo1 : oo2) * cu;
+        g[q] = keep * g[q] + (even + odd);
+        g[q + 1] = keep * g[q + 1] + (even - odd);
     }
 }
 
 // --------------------------------------------------------------- kernels
 
-// Inlet plane reduction (eq. potential). Each thread sums the consistency
-// sums of its inlet sites from the streamed (pulled) values; blocks write
-// FP64 partials; the last block to finish sums them in block order and sets
-// rho_in - 1 = (rho0 Q* + sum_i Kt_i) / A for the step kernel.
+// Inlet plane reduction (eq. potential) of the current state: each thread
+// sums the consistency sums of its inlet sites from the pulled values; blocks
+// write FP64 partials; the last block to finish sums them in block order into
+// s_carry[slot]. The fused step kernel turns it into rho_in and carries the
+// sum of the following step itself, so this kernel runs only when a run of
+// steps starts from a state the step kernel did not produce.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin,
                                                        const int32_t *__restrict__ nbr,
@@ -236,56 +407,141 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
     for (int i = threadIdx.x; i < (int)gridDim.x; i += BLOCK) s += a.kpart[i];
     s = block_sum<BLOCK>(s, lds);
     if (threadIdx.x == 0) {
-        DevState *st = a.st;
-        const double drho = (a.rho0 * st->q_target + s) / (double)a.a_in;
-        st->drho_in = drho;
-        const int64_t slot = st->step % a.hist_cap;
-        a.hist[slot * HIST_STRIDE + 0] = 1.0 + drho;
-        st->k_ticket = 0;
+        a.st->s_carry[a.slot] = s;
+        a.st->k_ticket = 0;
     }
 }
 
 // Fused step for every site: pull the 19 populations, apply the inlet or
 // outlet pressure condition where the site lies on z = 0 or z = nz-1, BGK
-// collide, store. Tiles holding boundary sites also reduce sum u_z (FP64)
-// and the last of them records Q_in, Q_out and advances the step counter.
+// collide, store. Each thread owns SC_V consecutive sites. Tiles holding
+// boundary sites also reduce sum u_z (FP64) and the last of them records Q_in,
+// Q_out and advances the step counter.
 // OBS: also write per-tile partials of mass, max |u|^2 and a non-finite flag.
-template <typename T, bool OBS>
-__global__ __launch_bounds__(BLOCK) void k_stream_collide(const T *__restrict__ fin,
-                                                          T *__restrict__ fout,
-                                                          const int32_t *__restrict__ nbr,
-                                                          StepArgs a)
+template <typename T, bool OBS, bool BUF>
+__global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict__ fin,
+                                                             T *__restrict__ fout,
+                                                             const int32_t *__restrict__ nbr,
+                                                             StepArgs a)
 {
     using R = typename Compute<T>::type;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int64_t s = (int64_t)tile * BLOCK + threadIdx.x;
+    constexpr int V = SC_V;
+    const int tile = (int)blockIdx.x;
+    const int64_t s0 = ((int64_t)tile * SC_BLOCK + threadIdx.x) * V;
     const int64_t npad = a.npad;
 
-    R g[19];
-    g[0] = (R)fin[s];
+    R g[V][19];
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t rf = make_rsrc(fin, a.f_bytes);
+        const __amdgpu_buffer_rsrc_t rn = make_rsrc(nbr, a.nbr_bytes);
+        const uint32_t vo = (uint32_t)s0 * (uint32_t)sizeof(T);
+        const uint32_t vi = (uint32_t)s0 * 4u;
+        {
+            R r[V];
+            buf_load_v<V, T>(rf, vo, 0u, r);
 #pragma unroll
-    for (int q = 1; q < 19; ++q) g[q] = (R)fin[nbr[(int64_t)(q - 1) * npad + s]];
+            for (int v = 0; v < V; ++v) g[v][0] = r[v];
+        }
+#pragma unroll
+        for (int q = 1; q < 19; ++q) {
+            int32_t idx[V];
+            buf_load_v<V, int32_t, int32_t, SC_IDX_AUX>(rn, vi, (uint32_t)(q - 1) * (uint32_t)npad * 4u, idx);
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                R r[1];
+                buf_load_v<1, T>(rf, (uint32_t)idx[v] * (uint32_t)sizeof(T), 0u, r);
+                g[v][q] = r[0];
+            }
+        }
+    } else {
+        {
+            R r[V];
+            load_v<V>(fin + s0, r);
+#pragma unroll
+            for (int v = 0; v < V; ++v) g[v][0] = r[v];
+        }
+#pragma unroll
+        for (int q = 1; q < 19; ++q) {
+            int32_t idx[V];
+            load_v<V>(nbr + (int64_t)(q - 1) * npad + s0, idx);
+#pragma unroll
+            for (int v = 0; v < V; ++v) g[v][q] = (R)fin[idx[v]];
+        }
+    }
 
     double uz_in = 0.0, uz_out = 0.0;
-    if (tile < a.nt_in && s < a.a_in) uz_in = inlet_condition(g, a.st->drho_in, a.rho0);
-    if (tile >= a.tout0 && s >= a.out0 && s < a.n)
-        uz_out = outlet_condition(g, a.st->drho_out, a.rho0);
-
-    R drho, ux, uy, uz;
-    bgk_collide(g, (R)a.st->omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
-
+    if (tile < a.nt_in) {
+        // eq. potential: rho_in - 1 = (rho0 Q* + sum_i Kt_i) / A
+        const double drho_in = (a.rho0 * a.st->q_target + a.st->s_carry[a.rd]) / (double)a.a_in;
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store((T)g[q], &fout[(int64_t)q * npad + s]);
+        for (int v = 0; v < V; ++v)
+            if (s0 + v < a.a_in) uz_in += inlet_condition(g[v], drho_in, a.rho0);
+    }
+    if (tile >= a.tout0) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (s0 + v >= a.out0 && s0 + v < a.n) uz_out += outlet_condition(g[v], a.st->drho_out, a.rho0);
+    }
 
-    __shared__ double lds[BLOCK / 64];
-    __shared__ float ldsf[BLOCK / 64];
-    __shared__ uint32_t ldsu[BLOCK / 64];
+    const R omega = (R)a.st->omega;
+    double m = 0.0;
+    float u2max = 0.f;
+    uint32_t bad = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        R drho, ux, uy, uz;
+        bgk_collide(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
+        if (OBS) {
+            m += (double)drho;
+            u2max = fmaxf(u2max, (float)(ux * ux + uy * uy + uz * uz));
+            bad |= !isfinite((double)drho + (double)ux + (double)uy + (double)uz);
+        }
+    }
+
+    // Contribution of this tile's post-collision populations to the next
+    // step's inlet sum: the pull table is a bijection, so each population of
+    // planes 0-1 that an inlet site will pull carries one fixed weight.
+    double s_next = 0.0;
+    if (tile < a.nt01) {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            if (s0 + v < a.n01) {
+                const uint64_t cw = a.kcoef[s0 + v];
+#pragma unroll
+                for (int q = 0; q < 19; ++q) {
+                    const uint32_t c = (uint32_t)(cw >> (2 * q)) & 3u;
+                    if (c) s_next += (double)c * (double)g[v][q];
+                }
+            }
+    }
+
+    if constexpr (BUF) {
+        const __amdgpu_buffer_rsrc_t ro = make_rsrc(fout, a.f_bytes);
+        const uint32_t vo = (uint32_t)s0 * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            R out[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) out[v] = g[v][q];
+            buf_store_v_nt<V, T>(ro, vo, (uint32_t)q * (uint32_t)npad * (uint32_t)sizeof(T), out);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            R out[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) out[v] = g[v][q];
+            store_v_nt<V>(fout + (int64_t)q * npad + s0, out);
+        }
+    }
+
+    __shared__ double lds[SC_BLOCK / 64];
+    __shared__ float ldsf[SC_BLOCK / 64];
+    __shared__ uint32_t ldsu[SC_BLOCK / 64];
     if (OBS) {
-        const double m = block_sum<BLOCK>((double)drho, lds);
-        const float u2 = (float)(ux * ux + uy * uy + uz * uz);
-        const uint32_t bad = !isfinite((double)drho + (double)ux + (double)uy + (double)uz);
-        float wm = wave_max(u2);
-        uint32_t wb = wave_or(bad);
+        m = block_sum<SC_BLOCK>(m, lds);
+        const float wm = wave_max(u2max);
+        const uint32_t wb = wave_or(bad);
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
             ldsf[w] = wm;
@@ -296,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const T *__restrict__ 
             float mm = 0.f;
             uint32_t bb = 0;
 #pragma unroll
-            for (int i = 0; i < BLOCK / 64; ++i) {
+            for (int i = 0; i < SC_BLOCK / 64; ++i) {
                 mm = fmaxf(mm, ldsf[i]);
                 bb |= ldsu[i];
             }
@@ -306,13 +562,18 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const T *__restrict__ 
         }
     }
 
-    const bool bnd_tile = a.flux_mode ? (tile < a.nt_in || tile >= a.tout0) : (tile == 0);
+    // Boundary tiles (planes 0-1 and the outlet plane; tile 0 in a closed
+    // box) reduce their partials; the last of them to finish records the
+    // step and hands the next inlet sum over.
+    const bool bnd_tile = a.flux_mode ? (tile < a.nt01 || tile >= a.tout0) : (tile == 0);
     if (!bnd_tile) return;
     __shared__ int is_last;
-    const double si = block_sum<BLOCK>(uz_in, lds);
-    const double so = block_sum<BLOCK>(uz_out, lds);
+    const double si = block_sum<SC_BLOCK>(uz_in, lds);
+    const double so = block_sum<SC_BLOCK>(uz_out, lds);
+    const double sn = block_sum<SC_BLOCK>(s_next, lds);
     if (threadIdx.x == 0) {
         if (tile < a.nt_in) a.bpart_in[tile] = si;
+        if (a.flux_mode && tile < a.nt01) a.spart[tile] = sn;
         if (a.flux_mode && tile >= a.tout0) a.bpart_out[tile - a.tout0] = so;
         __threadfence();
         const uint32_t prev = atomicAdd(&a.st->b_ticket, 1u);
@@ -321,19 +582,27 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const T *__restrict__ 
     __syncthreads();
     if (!is_last) return;
     __threadfence();
-    const int nt_out = a.flux_mode ? (int)((a.npad / BLOCK) - a.tout0) : 0;
-    double ti = 0.0, to = 0.0;
-    for (int i = threadIdx.x; i < a.nt_in; i += BLOCK) ti += a.bpart_in[i];
-    for (int i = threadIdx.x; i < nt_out; i += BLOCK) to += a.bpart_out[i];
-    ti = block_sum<BLOCK>(ti, lds);
-    to = block_sum<BLOCK>(to, lds);
+    const int nt_out = a.flux_mode ? (int)((a.npad / TILE) - a.tout0) : 0;
+    const int nt01 = a.flux_mode ? a.nt01 : 0;
+    double ti = 0.0, to = 0.0, tn = 0.0;
+    for (int i = threadIdx.x; i < a.nt_in; i += SC_BLOCK) ti += a.bpart_in[i];
+    for (int i = threadIdx.x; i < nt_out; i += SC_BLOCK) to += a.bpart_out[i];
+    for (int i = threadIdx.x; i < nt01; i += SC_BLOCK) tn += a.spart[i];
+    ti = block_sum<SC_BLOCK>(ti, lds);
+    to = block_sum<SC_BLOCK>(to, lds);
+    tn = block_sum<SC_BLOCK>(tn, lds);
     if (threadIdx.x == 0) {
         DevState *st = a.st;
         const int64_t t = st->step;
         double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
-        if (!a.flux_mode) h[0] = __builtin_nan("");
-        h[1] = a.flux_mode ? ti : __builtin_nan("");
-        h[2] = a.flux_mode ? to : __builtin_nan("");
+        if (a.flux_mode) {
+            h[0] = 1.0 + (a.rho0 * st->q_target + st->s_carry[a.rd]) / (double)a.a_in;
+            h[1] = ti;
+            h[2] = to;
+            st->s_carry[a.rd ^ 1] = tn;
+        } else {
+            h[0] = h[1] = h[2] = __builtin_nan("");
+        }
         h[3] = __builtin_nan("");
         h[4] = __builtin_nan("");
         h[5] = (double)(t + 1);
@@ -347,7 +616,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_collide(const T *__restrict__ 
 // finite or |u| exceeds the limit. One block.
 struct ObsArgs {
     int64_t n;
-    int32_t tiles, hist_cap;
+    int32_t tiles, hist_cap;   // tiles: number of per-tile partials to reduce
     double umax_limit;
     int32_t to_history;   // 1: record into the last step's history slot
     int32_t raise_flag;   // 1: a bad state sets the sticky watchdog flag
@@ -498,13 +767,13 @@ __global__ void k_set_u32(uint32_t *p, uint32_t v) { *p = v; }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Streaming copy, 16-byte lanes (calibration of attainable HBM bandwidth).
+// Streaming copy, one 16-byte element per thread (calibration of attainable
+// HBM bandwidth).
 __global__ __launch_bounds__(BLOCK) void k_copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                                   int64_t n16)
 {
-    for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < n16;
-         i += (int64_t)gridDim.x * BLOCK)
-        __builtin_nontemporal_store(src[i], &dst[i]);
+    const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
 }  // namespace flbm

@@ -9,7 +9,7 @@
 
 namespace flbm {
 
-int64_t padded_sites(int64_t n) { return ((n + 255) / 256) * 256; }
+int64_t padded_sites(int64_t n) { return ((n + 1023) / 1024) * 1024; }
 
 namespace {
 
@@ -66,6 +66,7 @@ std::string build_lattice(const uint8_t *solid_in, const LatticeSpec &spec, Latt
     L.n_pad = padded_sites(n);
     L.a_in = plane_count[0];
     L.a_out = plane_count[nz - 1];
+    L.n01 = plane_count[0] + plane_count[1];
     L.sentinel = 19 * L.n_pad;
     if (n == 0) {
         code = FLBM_EINVAL;
@@ -145,6 +146,28 @@ std::string build_lattice(const uint8_t *solid_in, const LatticeSpec &spec, Latt
     // Padding sites read their own (zero) slots so any thread may load them.
     for (int64_t s = n; s < npad; ++s)
         for (int q = 1; q < 19; ++q) L.nbr[(q - 1) * npad + s] = (int32_t)(q * npad + s);
+
+    if (spec.z_mode == FLBM_Z_FLUX) {
+        L.kcoef.assign(L.n01, 0);
+        for (int64_t i = 0; i < L.a_in; ++i) {
+            for (int q = 0; q < 19; ++q) {
+                const int c = d3q19::inlet_coeff(q);
+                if (!c) continue;
+                const int64_t idx = q == 0 ? i : L.nbr[(q - 1) * npad + i];
+                const int64_t qq = idx / npad, src = idx % npad;
+                if (idx == L.sentinel || src >= L.n01) {
+                    code = FLBM_EINVAL;
+                    return "inlet sum source outside planes 0-1";
+                }
+                uint64_t &w = L.kcoef[src];
+                if ((w >> (2 * qq)) & 3u) {
+                    code = FLBM_EINVAL;
+                    return "two inlet pulls read one population";
+                }
+                w |= (uint64_t)c << (2 * qq);
+            }
+        }
+    }
     return std::string();
 }
 

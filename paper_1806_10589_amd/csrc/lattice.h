@@ -26,12 +26,19 @@ struct LatticeSpec {
 //                        zero slot past the 19 rows.
 struct Lattice {
     int64_t n = 0, n_pad = 0, a_in = 0, a_out = 0;
+    int64_t n01 = 0;              // sites of planes z = 0 and z = 1
     int64_t sentinel = 0;
     std::vector<int32_t> coords;  // [n][3]
     std::vector<int32_t> nbr;     // [18][n_pad], row q-1 for direction q
+    // Flux mode: for each site of planes 0-1, bits 2q..2q+1 hold the weight
+    // (0, 1 or 2) with which its stored population q enters the next step's
+    // inlet consistency sum (eq. inlet: 1 for in-plane, 2 for populations
+    // leaving through the inlet; the pull table maps each such population to
+    // exactly one inlet site and direction).
+    std::vector<uint64_t> kcoef;  // [n01]
 };
 
-// Row length of every [q][site] array: a multiple of 256 sites.
+// Row length of every [q][site] array: a multiple of 1024 sites.
 int64_t padded_sites(int64_t n);
 
 // Builds the lattice. Returns an empty string on success, else an error text.
