@@ -23,6 +23,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in ("kernels.h", "engine.hip")]
 
 CONFIGS = {
     # name: (builder, lattice kwargs, description)
@@ -37,6 +39,38 @@ def bytes_per_lup(precision: str) -> int:
     written once in the storage type, plus 18 int32 pull indices."""
     elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
     return 19 * 2 * elem + 18 * 4
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, precision: str, n_sites: int):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary of this workload, or None when there is none or the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(PROFILE_DIR, f"k_stream_collide_{workload}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        per_site = float(vals["hbm_bytes_per_site"])
+    except (KeyError, ValueError):
+        return None
+    return round(per_site * n_sites)
 
 
 def make_workload(cfg):
@@ -155,7 +189,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(args.config, kw["precision"], n),
         "kernel": "k_stream_collide",
         "kernel_ms": round(ms_kernel, 5),
         "plane_kernel_ms": round(ms_plane, 5),
