@@ -156,10 +156,12 @@ flbm_status flbm_sync(flbm_ctx *c);
 flbm_status flbm_get_boundary(flbm_ctx *c, double *q_in, double *q_out, double *rho_in,
                               double *rho_out);
 
-/* Per-step FP64 history of the last n steps, oldest first, 5 doubles per
- * step: rho_in, Q_in, Q_out, total mass, max|u|. Mass and max|u| are NaN on
- * steps that were not watchdog points. n must not exceed the number of steps
- * taken nor the ring capacity (flbm_history_capacity). Synchronises. */
+/* Per-step FP64 history of the last n steps, oldest first, 7 doubles per
+ * step: rho_in, Q_in, Q_out, total mass, max|u|, sum N_A, sum N_B. Mass,
+ * max|u| and the colour sums are NaN on steps that were not watchdog points
+ * (the colour sums always for the single-fluid model). n must not exceed the
+ * number of steps taken nor the ring capacity (flbm_history_capacity).
+ * Synchronises. */
 flbm_status flbm_get_history(flbm_ctx *c, double *buf, int32_t n);
 flbm_status flbm_history_capacity(const flbm_ctx *c, int32_t *cap);
 
@@ -179,6 +181,23 @@ flbm_status flbm_read_fields(flbm_ctx *c, double *rho, double *ux, double *uy, d
 flbm_status flbm_read_distributions(flbm_ctx *c, double *f);
 flbm_status flbm_write_distributions(flbm_ctx *c, const double *f);
 
+/* Two-fluid colour model (Appendix A; FLBM_COLOUR contexts only, else
+ * FLBM_ESTATE). The colours A (non-wetting) and B (wetting) are D3Q7
+ * distributions over the velocities q = 0..6 with weights 1/3, 1/9.
+ *
+ * flbm_init_colour: momentum at rest (rho = 1, u = 0) and A_q = w_q na[s],
+ *   B_q = w_q nb[s] from host FP64 arrays of n_sites colour densities; resets
+ *   the step counter, history and watchdog flag.
+ * flbm_read_colour / flbm_write_colour: host FP64 [7][n_sites] each, site
+ *   order; writing resets the step counter.
+ * flbm_read_phase: phi = (N_A - N_B)/(N_A + N_B) of the stored state, host
+ *   FP64 [n_sites].
+ * All synchronise. */
+flbm_status flbm_init_colour(flbm_ctx *c, const double *na, const double *nb);
+flbm_status flbm_read_colour(flbm_ctx *c, double *A, double *B);
+flbm_status flbm_write_colour(flbm_ctx *c, const double *A, const double *B);
+flbm_status flbm_read_phase(flbm_ctx *c, double *phi);
+
 /* Host copy of the pull table, int32 [18][n_sites] (row q-1 for direction
  * q = 1..18): the flat index into a [19][n_pad] distribution array that
  * streams into (q, site) -- q*n_pad + source site, opp(q)*n_pad + site for
@@ -187,9 +206,10 @@ flbm_status flbm_write_distributions(flbm_ctx *c, const double *f);
 flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
 
 /* Raw checkpoint of the stored state: flbm_state_bytes gives the size; save
- * copies the current distribution buffer (storage precision, deviations)
- * and the step count to host memory; load restores it, so that a resumed run
- * is bitwise identical to an uninterrupted one. Synchronise. */
+ * copies the current distribution buffers (storage precision: f as
+ * deviations, then A and B for the colour model), the step count and the
+ * carried inlet sum to host memory; load restores them, so that a resumed
+ * run is bitwise identical to an uninterrupted one. Synchronise. */
 flbm_status flbm_state_bytes(const flbm_ctx *c, size_t *bytes);
 flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes);
 flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes);

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/fluxlbm.h"
+#include "colour.h"
 #include "kernels.h"
 #include "lattice.h"
 
@@ -68,6 +69,11 @@ struct flbm_ctx {
     uint32_t *obs_bad = nullptr;
     double *hist = nullptr;
     double *fields = nullptr;
+    // two-fluid colour model
+    bool colour = false;
+    void *ca[2] = {nullptr, nullptr}, *cb[2] = {nullptr, nullptr};  // [7][n_pad] each
+    void *na = nullptr, *nb = nullptr, *phi = nullptr;              // [n_pad] each
+    double *obs_na = nullptr, *obs_nb = nullptr;
 
     // host bookkeeping
     int64_t steps = 0;
@@ -120,6 +126,14 @@ size_t carve(flbm_ctx *c, char *base)
     char *ob = take((size_t)c->obs_slots * sizeof(uint32_t));
     char *hi = take((size_t)HIST_CAP * HIST_STRIDE * sizeof(double));
     char *fl = take((size_t)4 * npad * sizeof(double));
+    char *cc[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    char *on = nullptr, *ob2 = nullptr;
+    if (c->colour) {
+        for (int i = 0; i < 4; ++i) cc[i] = take((size_t)7 * npad * c->elem);
+        for (int i = 4; i < 7; ++i) cc[i] = take((size_t)npad * c->elem);
+        on = take((size_t)c->obs_slots * sizeof(double));
+        ob2 = take((size_t)c->obs_slots * sizeof(double));
+    }
     if (base) {
         c->f[0] = f0;
         c->f[1] = f1;
@@ -135,6 +149,17 @@ size_t carve(flbm_ctx *c, char *base)
         c->obs_bad = (uint32_t *)ob;
         c->hist = (double *)hi;
         c->fields = (double *)fl;
+        if (c->colour) {
+            c->ca[0] = cc[0];
+            c->ca[1] = cc[1];
+            c->cb[0] = cc[2];
+            c->cb[1] = cc[3];
+            c->na = cc[4];
+            c->nb = cc[5];
+            c->phi = cc[6];
+            c->obs_na = (double *)on;
+            c->obs_nb = (double *)ob2;
+        }
     }
     return off;
 }
@@ -166,6 +191,8 @@ StepArgs step_args(const flbm_ctx *c)
     a.obs_mass = c->obs_mass;
     a.obs_umax2 = c->obs_umax2;
     a.obs_bad = c->obs_bad;
+    a.obs_na = c->obs_na;
+    a.obs_nb = c->obs_nb;
     a.hist = c->hist;
     return a;
 }
@@ -194,8 +221,55 @@ ObsArgs obs_args(const flbm_ctx *c, int to_history, int partials)
     a.obs_mass = c->obs_mass;
     a.obs_umax2 = c->obs_umax2;
     a.obs_bad = c->obs_bad;
+    a.obs_na = to_history ? c->obs_na : nullptr;
+    a.obs_nb = to_history ? c->obs_nb : nullptr;
     a.hist = c->hist;
     return a;
+}
+
+// The two launches of a colour step from buffer `from`.
+template <typename T>
+void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
+{
+    PhaseArgs p{};
+    p.n = c->lat.n;
+    p.npad = c->lat.n_pad;
+    const bool flux = c->p.z_mode == FLBM_Z_FLUX;
+    p.a_in = flux ? c->lat.a_in : 0;
+    p.out0 = flux ? c->lat.n - c->lat.a_out : c->lat.n;
+    p.sentinel = c->lat.sentinel;
+    p.flux_mode = flux;
+    p.rd = from;
+    p.rho0 = c->p.rho0;
+    p.st = c->st;
+    p.nbr = c->nbr;
+    p.fin = c->f[from];
+    p.ain = c->ca[from];
+    p.bin = c->cb[from];
+    p.aout = c->ca[from ^ 1];
+    p.bout = c->cb[from ^ 1];
+    p.na = c->na;
+    p.nb = c->nb;
+    p.phi = c->phi;
+    hipLaunchKernelGGL(k_phase<T>, dim3(c->blocks256), dim3(BLOCK), 0, s, p);
+    StepArgs a = step_args(c);
+    a.rd = from;
+    ColourStepArgs cs{};
+    cs.alpha = c->p.alpha;
+    cs.beta = c->p.beta;
+    cs.phi_solid = c->p.phi_solid;
+    cs.sentinel = c->lat.sentinel;
+    cs.na = c->na;
+    cs.nb = c->nb;
+    cs.phi = c->phi;
+    cs.aout = c->ca[from ^ 1];
+    cs.bout = c->cb[from ^ 1];
+    const T *fin = (const T *)c->f[from];
+    T *fout = (T *)c->f[from ^ 1];
+    if (obs)
+        hipLaunchKernelGGL((k_colour<T, true>), dim3(c->tiles), dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
+    else
+        hipLaunchKernelGGL((k_colour<T, false>), dim3(c->tiles), dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
 }
 
 // The fused kernel in its four variants: with or without the watchdog
@@ -231,6 +305,14 @@ void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
 
 void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
 {
+    if (c->colour) {
+        if (is_fp64(c))
+            launch_colour_step<double>(c, s, from, obs);
+        else
+            launch_colour_step<float>(c, s, from, obs);
+        if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
+        return;
+    }
     if (is_fp64(c))
         launch_step<double>(c, s, from, obs);
     else
@@ -332,6 +414,13 @@ flbm_status setup_device(flbm_ctx *c, void *mem)
         HIPCHK(c, hipMemcpyAsync(c->kcoef, c->lat.kcoef.data(), c->lat.kcoef.size() * sizeof(uint64_t),
                                  hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->kpart, 0, PLANE_MAX_BLOCKS * sizeof(double), c->stream));
+    if (c->colour) {
+        for (int i = 0; i < 2; ++i) {
+            HIPCHK(c, hipMemsetAsync(c->ca[i], 0, (size_t)7 * c->lat.n_pad * c->elem, c->stream));
+            HIPCHK(c, hipMemsetAsync(c->cb[i], 0, (size_t)7 * c->lat.n_pad * c->elem, c->stream));
+        }
+        HIPCHK(c, hipMemsetAsync(c->phi, 0, (size_t)c->lat.n_pad * c->elem, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->ready = true;
     c->cur = 0;
@@ -359,7 +448,10 @@ flbm_status check_params(const flbm_params *p, std::string &why)
     if (p->z_mode < FLBM_Z_FLUX || p->z_mode > FLBM_Z_WALL) return why = "unknown z_mode", FLBM_EINVAL;
     if (p->precision != FLBM_FP64 && p->precision != FLBM_FP32)
         return why = "precision not available", FLBM_EINVAL;
-    if (p->model != FLBM_BGK) return why = "model not available", FLBM_EINVAL;
+    if (p->model != FLBM_BGK && p->model != FLBM_COLOUR) return why = "unknown model", FLBM_EINVAL;
+    if (p->model == FLBM_COLOUR && (!std::isfinite(p->alpha) || !std::isfinite(p->beta) ||
+                                    !std::isfinite(p->phi_solid)))
+        return why = "colour parameters must be finite", FLBM_EINVAL;
     if (p->watchdog_every < 0) return why = "watchdog_every must be >= 0", FLBM_EINVAL;
     if (!std::isfinite(p->q_target) || !std::isfinite(p->rho_out) || !(p->rho_out > 0.0))
         return why = "q_target and rho_out must be finite, rho_out positive", FLBM_EINVAL;
@@ -411,6 +503,7 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
     c->spec.reservoir_layers = p->reservoir_layers;
     c->stream = (hipStream_t)hip_stream;
     c->elem = is_fp64(c) ? 8 : 4;
+    c->colour = p->model == FLBM_COLOUR;
     int code = FLBM_OK;
     std::string e = build_lattice(solid_mask, c->spec, c->lat, code);
     if (!e.empty()) {
@@ -505,10 +598,16 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr)
     return FLBM_OK;
 }
 
+// Distributions in a checkpoint: f, then A and B for the colour model.
+static size_t state_f_bytes(const flbm_ctx *c)
+{
+    return (size_t)(c->colour ? 19 + 14 : 19) * c->lat.n_pad * c->elem;
+}
+
 flbm_status flbm_state_bytes(const flbm_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return FLBM_EINVAL;
-    *bytes = (size_t)19 * c->lat.n_pad * c->elem + 3 * sizeof(int64_t);
+    *bytes = state_f_bytes(c) + 3 * sizeof(int64_t);
     return FLBM_OK;
 }
 
@@ -523,12 +622,17 @@ struct StateTrailer {
 flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes)
 {
     if (!c || !host) return FLBM_EINVAL;
-    const size_t fb = (size_t)19 * c->lat.n_pad * c->elem;
+    const size_t fb = state_f_bytes(c), f19 = (size_t)19 * c->lat.n_pad * c->elem;
     if (bytes < fb + sizeof(StateTrailer)) return fail(c, FLBM_EBOUND, "host buffer too small");
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(host, c->f[c->cur], fb, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(host, c->f[c->cur], f19, hipMemcpyDeviceToHost));
+    if (c->colour) {
+        const size_t c7 = (size_t)7 * c->lat.n_pad * c->elem;
+        HIPCHK(c, hipMemcpy((char *)host + f19, c->ca[c->cur], c7, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy((char *)host + f19 + c7, c->cb[c->cur], c7, hipMemcpyDeviceToHost));
+    }
     DevState d{};
     HIPCHK(c, hipMemcpy(&d, c->st, sizeof(d), hipMemcpyDeviceToHost));
     StateTrailer tr{c->steps, c->need_plane ? 0 : 1, d.s_carry[c->cur]};
@@ -539,12 +643,17 @@ flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes)
 flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
 {
     if (!c || !host) return FLBM_EINVAL;
-    const size_t fb = (size_t)19 * c->lat.n_pad * c->elem;
+    const size_t fb = state_f_bytes(c), f19 = (size_t)19 * c->lat.n_pad * c->elem;
     if (bytes < fb + sizeof(StateTrailer)) return fail(c, FLBM_EBOUND, "host buffer too small");
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipMemcpy(c->f[c->cur], host, fb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->f[c->cur], host, f19, hipMemcpyHostToDevice));
+    if (c->colour) {
+        const size_t c7 = (size_t)7 * c->lat.n_pad * c->elem;
+        HIPCHK(c, hipMemcpy(c->ca[c->cur], (const char *)host + f19, c7, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->cb[c->cur], (const char *)host + f19 + c7, c7, hipMemcpyHostToDevice));
+    }
     rc = reset_state(c);
     if (rc) return rc;
     StateTrailer tr{};
@@ -557,6 +666,107 @@ flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
         HIPCHK(c, hipMemcpy(&c->st->s_carry[c->cur], &tr.s_carry, sizeof(double), hipMemcpyHostToDevice));
         c->need_plane = false;
     }
+    return FLBM_OK;
+}
+
+// Host [7][n] FP64 colour distributions <-> device [7][n_pad] storage.
+static flbm_status write_colour_buffer(flbm_ctx *c, void *dst, const double *src)
+{
+    const int64_t n = c->lat.n, npad = c->lat.n_pad;
+    if (is_fp64(c)) {
+        std::vector<double> h((size_t)7 * npad, 0.0);
+        for (int q = 0; q < 7; ++q)
+            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = src[q * n + s];
+        HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> h((size_t)7 * npad, 0.0f);
+        for (int q = 0; q < 7; ++q)
+            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = (float)src[q * n + s];
+        HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return FLBM_OK;
+}
+
+static flbm_status read_colour_buffer(flbm_ctx *c, const void *src, double *dst)
+{
+    const int64_t n = c->lat.n, npad = c->lat.n_pad;
+    if (is_fp64(c)) {
+        std::vector<double> h((size_t)7 * npad);
+        HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int q = 0; q < 7; ++q)
+            for (int64_t s = 0; s < n; ++s) dst[q * n + s] = h[q * npad + s];
+    } else {
+        std::vector<float> h((size_t)7 * npad);
+        HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(float), hipMemcpyDeviceToHost));
+        for (int q = 0; q < 7; ++q)
+            for (int64_t s = 0; s < n; ++s) dst[q * n + s] = (double)h[q * npad + s];
+    }
+    return FLBM_OK;
+}
+
+flbm_status flbm_init_colour(flbm_ctx *c, const double *na, const double *nb)
+{
+    if (!c || !na || !nb) return FLBM_EINVAL;
+    if (!c->colour) return fail(c, FLBM_ESTATE, "not a colour-model context");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    rc = fill_equilibrium(c, 1.0, 0.0, 0.0, 0.0);
+    if (rc) return rc;
+    const int64_t n = c->lat.n;
+    std::vector<double> a((size_t)7 * n), b((size_t)7 * n);
+    for (int q = 0; q < 7; ++q)
+        for (int64_t s = 0; s < n; ++s) {
+            a[q * n + s] = d3q19::weight7(q) * na[s];
+            b[q * n + s] = d3q19::weight7(q) * nb[s];
+        }
+    rc = write_colour_buffer(c, c->ca[c->cur], a.data());
+    if (rc) return rc;
+    return write_colour_buffer(c, c->cb[c->cur], b.data());
+}
+
+flbm_status flbm_read_colour(flbm_ctx *c, double *A, double *B)
+{
+    if (!c || !A || !B) return FLBM_EINVAL;
+    if (!c->colour) return fail(c, FLBM_ESTATE, "not a colour-model context");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    rc = read_colour_buffer(c, c->ca[c->cur], A);
+    if (rc) return rc;
+    return read_colour_buffer(c, c->cb[c->cur], B);
+}
+
+flbm_status flbm_write_colour(flbm_ctx *c, const double *A, const double *B)
+{
+    if (!c || !A || !B) return FLBM_EINVAL;
+    if (!c->colour) return fail(c, FLBM_ESTATE, "not a colour-model context");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    rc = write_colour_buffer(c, c->ca[c->cur], A);
+    if (rc) return rc;
+    rc = write_colour_buffer(c, c->cb[c->cur], B);
+    if (rc) return rc;
+    return reset_state(c);
+}
+
+flbm_status flbm_read_phase(flbm_ctx *c, double *phi)
+{
+    if (!c || !phi) return FLBM_EINVAL;
+    if (!c->colour) return fail(c, FLBM_ESTATE, "not a colour-model context");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    if (is_fp64(c))
+        hipLaunchKernelGGL(k_phase_of_state<double>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
+                           (const double *)c->ca[c->cur], (const double *)c->cb[c->cur], c->lat.n, c->lat.n_pad,
+                           c->fields);
+    else
+        hipLaunchKernelGGL(k_phase_of_state<float>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
+                           (const float *)c->ca[c->cur], (const float *)c->cb[c->cur], c->lat.n, c->lat.n_pad,
+                           c->fields);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(phi, c->fields, c->lat.n * sizeof(double), hipMemcpyDeviceToHost));
     return FLBM_OK;
 }
 
@@ -673,7 +883,9 @@ flbm_status flbm_get_history(flbm_ctx *c, double *buf, int32_t n)
     for (int32_t i = 0; i < n; ++i) {
         const int64_t t = c->steps - n + i;  // 0-based step index
         const double *r = &h[(size_t)(t % HIST_CAP) * HIST_STRIDE];
-        for (int k = 0; k < 5; ++k) buf[5 * (size_t)i + k] = r[k];
+        for (int k = 0; k < 5; ++k) buf[7 * (size_t)i + k] = r[k];
+        buf[7 * (size_t)i + 5] = r[6];
+        buf[7 * (size_t)i + 6] = r[7];
     }
     return FLBM_OK;
 }
@@ -688,7 +900,7 @@ flbm_status flbm_get_boundary(flbm_ctx *c, double *q_in, double *q_out, double *
         if (rho_in) *rho_in = NAN;
         return FLBM_OK;
     }
-    double r[5];
+    double r[7];
     flbm_status rc = flbm_get_history(c, r, 1);
     if (rc) return rc;
     if (rho_in) *rho_in = r[0];

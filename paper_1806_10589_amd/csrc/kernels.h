@@ -82,6 +82,7 @@ struct StepArgs {
     double *obs_mass;               // per-tile sums of rho - 1
     float *obs_umax2;               // per-tile max |u|^2
     uint32_t *obs_bad;              // per-tile non-finite flag
+    double *obs_na, *obs_nb;        // per-tile colour sums (two-fluid model)
     double *hist;
 };
 
@@ -273,14 +274,33 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
 // (Appendix B; u_x = u_y = 0): u_z from the consistency condition eq. inlet,
 // f5 by non-equilibrium bounce-back, f11, f14, f15, f18 from the simplified
 // Hecht-Harting rows. Arithmetic in FP64. Returns u_z.
+// u_z at an inlet site from the consistency condition (eq. inlet) with the
+// known populations (deviations) and inlet density 1 + drho_in.
 template <typename R>
-__device__ __forceinline__ double inlet_condition(R (&g)[19], double drho_in, double rho0)
+__device__ __forceinline__ double inlet_velocity(const R (&g)[19], double drho_in, double rho0)
 {
     double k = 0.0;
 #pragma unroll
     for (int q = 0; q < 19; ++q)
         if (d3q19::inlet_coeff(q)) k += d3q19::inlet_coeff(q) * (double)g[q];
-    const double uz = (drho_in - k) / rho0;
+    return (drho_in - k) / rho0;
+}
+
+// u_z at an outlet site with outlet density 1 + drho_out.
+template <typename R>
+__device__ __forceinline__ double outlet_velocity(const R (&g)[19], double drho_out, double rho0)
+{
+    double k = 0.0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q)
+        if (d3q19::outlet_coeff(q)) k += d3q19::outlet_coeff(q) * (double)g[q];
+    return (k - drho_out) / rho0;
+}
+
+template <typename R>
+__device__ __forceinline__ double inlet_condition(R (&g)[19], double drho_in, double rho0)
+{
+    const double uz = inlet_velocity(g, drho_in, rho0);
     const double nx = 0.5 * ((double)g[1] + (double)g[7] + (double)g[9] -
                              ((double)g[2] + (double)g[10] + (double)g[8]));
     const double ny = 0.5 * ((double)g[3] + (double)g[7] + (double)g[10] -
@@ -299,11 +319,7 @@ __device__ __forceinline__ double inlet_condition(R (&g)[19], double drho_in, do
 template <typename R>
 __device__ __forceinline__ double outlet_condition(R (&g)[19], double drho_out, double rho0)
 {
-    double k = 0.0;
-#pragma unroll
-    for (int q = 0; q < 19; ++q)
-        if (d3q19::outlet_coeff(q)) k += d3q19::outlet_coeff(q) * (double)g[q];
-    const double uz = (k - drho_out) / rho0;
+    const double uz = outlet_velocity(g, drho_out, rho0);
     const double nx = 0.5 * ((double)g[1] + (double)g[7] + (double)g[9] -
                              ((double)g[2] + (double)g[10] + (double)g[8]));
     const double ny = 0.5 * ((double)g[3] + (double)g[7] + (double)g[10] -
@@ -409,6 +425,104 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
     if (threadIdx.x == 0) {
         a.st->s_carry[a.slot] = s;
         a.st->k_ticket = 0;
+    }
+}
+
+// Shared tail of the step kernels (NT threads per tile). OBS: write the
+// tile's watchdog partials (sum of rho - 1, max |u|^2, non-finite flag).
+// Boundary tiles (planes 0-1 and the outlet plane; tile 0 in a closed box)
+// reduce their u_z sums and their share of the next inlet sum; the last of
+// them to finish records the step (rho_in, Q_in, Q_out), hands the next
+// inlet sum over and advances the step counter.
+// COLOUR: also the tile's sums of the two colour densities.
+template <int NT, bool OBS, bool COLOUR = false>
+__device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_out, double s_next, double m,
+                                              float u2max, uint32_t bad, const StepArgs &a,
+                                              double na_sum = 0.0, double nb_sum = 0.0)
+{
+    __shared__ double lds[NT / 64];
+    __shared__ float ldsf[NT / 64];
+    __shared__ uint32_t ldsu[NT / 64];
+    if (OBS && COLOUR) {
+        na_sum = block_sum<NT>(na_sum, lds);
+        nb_sum = block_sum<NT>(nb_sum, lds);
+        if (threadIdx.x == 0) {
+            a.obs_na[tile] = na_sum;
+            a.obs_nb[tile] = nb_sum;
+        }
+    }
+    if (OBS) {
+        m = block_sum<NT>(m, lds);
+        const float wm = wave_max(u2max);
+        const uint32_t wb = wave_or(bad);
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            ldsf[w] = wm;
+            ldsu[w] = wb;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float mm = 0.f;
+            uint32_t bb = 0;
+#pragma unroll
+            for (int i = 0; i < NT / 64; ++i) {
+                mm = fmaxf(mm, ldsf[i]);
+                bb |= ldsu[i];
+            }
+            a.obs_mass[tile] = m;
+            a.obs_umax2[tile] = mm;
+            a.obs_bad[tile] = bb;
+        }
+    }
+
+    // Boundary tiles (planes 0-1 and the outlet plane; tile 0 in a closed
+    // box) reduce their partials; the last of them to finish records the
+    // step and hands the next inlet sum over.
+    const bool bnd_tile = a.flux_mode ? (tile < a.nt01 || tile >= a.tout0) : (tile == 0);
+    if (!bnd_tile) return;
+    __shared__ int is_last;
+    const double si = block_sum<NT>(uz_in, lds);
+    const double so = block_sum<NT>(uz_out, lds);
+    const double sn = block_sum<NT>(s_next, lds);
+    if (threadIdx.x == 0) {
+        if (tile < a.nt_in) a.bpart_in[tile] = si;
+        if (a.flux_mode && tile < a.nt01) a.spart[tile] = sn;
+        if (a.flux_mode && tile >= a.tout0) a.bpart_out[tile - a.tout0] = so;
+        __threadfence();
+        const uint32_t prev = atomicAdd(&a.st->b_ticket, 1u);
+        is_last = (prev == (uint32_t)a.n_bnd - 1);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    const int nt_out = a.flux_mode ? (int)((a.npad / TILE) - a.tout0) : 0;
+    const int nt01 = a.flux_mode ? a.nt01 : 0;
+    double ti = 0.0, to = 0.0, tn = 0.0;
+    for (int i = threadIdx.x; i < a.nt_in; i += NT) ti += a.bpart_in[i];
+    for (int i = threadIdx.x; i < nt_out; i += NT) to += a.bpart_out[i];
+    for (int i = threadIdx.x; i < nt01; i += NT) tn += a.spart[i];
+    ti = block_sum<NT>(ti, lds);
+    to = block_sum<NT>(to, lds);
+    tn = block_sum<NT>(tn, lds);
+    if (threadIdx.x == 0) {
+        DevState *st = a.st;
+        const int64_t t = st->step;
+        double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
+        if (a.flux_mode) {
+            h[0] = 1.0 + (a.rho0 * st->q_target + st->s_carry[a.rd]) / (double)a.a_in;
+            h[1] = ti;
+            h[2] = to;
+            st->s_carry[a.rd ^ 1] = tn;
+        } else {
+            h[0] = h[1] = h[2] = __builtin_nan("");
+        }
+        h[3] = __builtin_nan("");
+        h[4] = __builtin_nan("");
+        h[5] = (double)(t + 1);
+        h[6] = __builtin_nan("");
+        h[7] = __builtin_nan("");
+        st->step = t + 1;
+        st->b_ticket = 0;
     }
 }
 
@@ -535,80 +649,7 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
         }
     }
 
-    __shared__ double lds[SC_BLOCK / 64];
-    __shared__ float ldsf[SC_BLOCK / 64];
-    __shared__ uint32_t ldsu[SC_BLOCK / 64];
-    if (OBS) {
-        m = block_sum<SC_BLOCK>(m, lds);
-        const float wm = wave_max(u2max);
-        const uint32_t wb = wave_or(bad);
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) {
-            ldsf[w] = wm;
-            ldsu[w] = wb;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            float mm = 0.f;
-            uint32_t bb = 0;
-#pragma unroll
-            for (int i = 0; i < SC_BLOCK / 64; ++i) {
-                mm = fmaxf(mm, ldsf[i]);
-                bb |= ldsu[i];
-            }
-            a.obs_mass[tile] = m;
-            a.obs_umax2[tile] = mm;
-            a.obs_bad[tile] = bb;
-        }
-    }
-
-    // Boundary tiles (planes 0-1 and the outlet plane; tile 0 in a closed
-    // box) reduce their partials; the last of them to finish records the
-    // step and hands the next inlet sum over.
-    const bool bnd_tile = a.flux_mode ? (tile < a.nt01 || tile >= a.tout0) : (tile == 0);
-    if (!bnd_tile) return;
-    __shared__ int is_last;
-    const double si = block_sum<SC_BLOCK>(uz_in, lds);
-    const double so = block_sum<SC_BLOCK>(uz_out, lds);
-    const double sn = block_sum<SC_BLOCK>(s_next, lds);
-    if (threadIdx.x == 0) {
-        if (tile < a.nt_in) a.bpart_in[tile] = si;
-        if (a.flux_mode && tile < a.nt01) a.spart[tile] = sn;
-        if (a.flux_mode && tile >= a.tout0) a.bpart_out[tile - a.tout0] = so;
-        __threadfence();
-        const uint32_t prev = atomicAdd(&a.st->b_ticket, 1u);
-        is_last = (prev == (uint32_t)a.n_bnd - 1);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    const int nt_out = a.flux_mode ? (int)((a.npad / TILE) - a.tout0) : 0;
-    const int nt01 = a.flux_mode ? a.nt01 : 0;
-    double ti = 0.0, to = 0.0, tn = 0.0;
-    for (int i = threadIdx.x; i < a.nt_in; i += SC_BLOCK) ti += a.bpart_in[i];
-    for (int i = threadIdx.x; i < nt_out; i += SC_BLOCK) to += a.bpart_out[i];
-    for (int i = threadIdx.x; i < nt01; i += SC_BLOCK) tn += a.spart[i];
-    ti = block_sum<SC_BLOCK>(ti, lds);
-    to = block_sum<SC_BLOCK>(to, lds);
-    tn = block_sum<SC_BLOCK>(tn, lds);
-    if (threadIdx.x == 0) {
-        DevState *st = a.st;
-        const int64_t t = st->step;
-        double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
-        if (a.flux_mode) {
-            h[0] = 1.0 + (a.rho0 * st->q_target + st->s_carry[a.rd]) / (double)a.a_in;
-            h[1] = ti;
-            h[2] = to;
-            st->s_carry[a.rd ^ 1] = tn;
-        } else {
-            h[0] = h[1] = h[2] = __builtin_nan("");
-        }
-        h[3] = __builtin_nan("");
-        h[4] = __builtin_nan("");
-        h[5] = (double)(t + 1);
-        st->step = t + 1;
-        st->b_ticket = 0;
-    }
+    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a);
 }
 
 // Reduce the per-tile observables of the last step into its history record
@@ -624,6 +665,7 @@ struct ObsArgs {
     const double *obs_mass;
     const float *obs_umax2;
     const uint32_t *obs_bad;
+    const double *obs_na, *obs_nb;  // null for the single-fluid model
     double *hist;
 };
 
@@ -643,6 +685,15 @@ __global__ __launch_bounds__(OBS_BLOCK) void k_obs_finalize(ObsArgs a)
         bad |= a.obs_bad[i];
     }
     m = block_sum<OBS_BLOCK>(m, lds);
+    double sa = 0.0, sb = 0.0;
+    if (a.obs_na) {
+        for (int i = threadIdx.x; i < a.tiles; i += OBS_BLOCK) {
+            sa += a.obs_na[i];
+            sb += a.obs_nb[i];
+        }
+        sa = block_sum<OBS_BLOCK>(sa, lds);
+        sb = block_sum<OBS_BLOCK>(sb, lds);
+    }
     u2 = wave_max(u2);
     bad = wave_or(bad);
     const int w = threadIdx.x >> 6;
@@ -669,6 +720,10 @@ __global__ __launch_bounds__(OBS_BLOCK) void k_obs_finalize(ObsArgs a)
             double *h = a.hist + ((st->step - 1) % a.hist_cap) * HIST_STRIDE;
             h[3] = mass;
             h[4] = umax;
+            if (a.obs_na) {
+                h[6] = sa;
+                h[7] = sb;
+            }
         }
     }
 }

@@ -83,6 +83,10 @@ _SIGS = {
     "flbm_read_fields": [_P, _P, _P, _P, _P],
     "flbm_read_distributions": [_P, _P],
     "flbm_write_distributions": [_P, _P],
+    "flbm_init_colour": [_P, _P, _P],
+    "flbm_read_colour": [_P, _P, _P],
+    "flbm_write_colour": [_P, _P, _P],
+    "flbm_read_phase": [_P, _P],
     "flbm_get_pull_table": [_P, _P],
     "flbm_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "flbm_save_state": [_P, _P, ctypes.c_size_t],
@@ -208,7 +212,8 @@ def flbm_get_boundary(ctx):
 
 
 def flbm_get_history(ctx, n: int) -> np.ndarray:
-    out = np.empty((n, 5), np.float64)
+    """(n, 7): rho_in, Q_in, Q_out, mass, max|u|, sum N_A, sum N_B."""
+    out = np.empty((n, 7), np.float64)
     _check(load_library().flbm_get_history(ctx, out.ctypes.data, int(n)), "flbm_get_history", ctx)
     return out
 
@@ -240,6 +245,31 @@ def flbm_read_distributions(ctx, n_sites: int) -> np.ndarray:
 def flbm_write_distributions(ctx, f: np.ndarray) -> None:
     f = np.ascontiguousarray(f, dtype=np.float64)
     _check(load_library().flbm_write_distributions(ctx, f.ctypes.data), "flbm_write_distributions", ctx)
+
+
+def flbm_init_colour(ctx, na: np.ndarray, nb: np.ndarray) -> None:
+    na = np.ascontiguousarray(na, dtype=np.float64)
+    nb = np.ascontiguousarray(nb, dtype=np.float64)
+    _check(load_library().flbm_init_colour(ctx, na.ctypes.data, nb.ctypes.data), "flbm_init_colour", ctx)
+
+
+def flbm_read_colour(ctx, n_sites: int):
+    A = np.empty((7, n_sites), np.float64)
+    B = np.empty((7, n_sites), np.float64)
+    _check(load_library().flbm_read_colour(ctx, A.ctypes.data, B.ctypes.data), "flbm_read_colour", ctx)
+    return A, B
+
+
+def flbm_write_colour(ctx, A: np.ndarray, B: np.ndarray) -> None:
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    _check(load_library().flbm_write_colour(ctx, A.ctypes.data, B.ctypes.data), "flbm_write_colour", ctx)
+
+
+def flbm_read_phase(ctx, n_sites: int) -> np.ndarray:
+    out = np.empty(n_sites, np.float64)
+    _check(load_library().flbm_read_phase(ctx, out.ctypes.data), "flbm_read_phase", ctx)
+    return out
 
 
 def flbm_get_pull_table(ctx, n_sites: int) -> np.ndarray:
@@ -406,6 +436,18 @@ class Lattice:
 
     def write_distributions(self, f):
         flbm_write_distributions(self.ctx, f)
+
+    def init_colour(self, na, nb):
+        flbm_init_colour(self.ctx, na, nb)
+
+    def read_colour(self):
+        return flbm_read_colour(self.ctx, self.n_sites)
+
+    def write_colour(self, A, B):
+        flbm_write_colour(self.ctx, A, B)
+
+    def phase(self):
+        return flbm_read_phase(self.ctx, self.n_sites)
 
     def pull_table(self):
         return flbm_get_pull_table(self.ctx, self.n_sites)

@@ -25,8 +25,9 @@ def random_state(mask, seed, amp=0.05):
 
 
 def dense_to_sites(mask, f_dense):
-    """Dense (nz, ny, nx, 19) -> site-ordered (19, n)."""
-    return np.ascontiguousarray(f_dense.reshape(-1, 19)[inputs.pore_sites(mask)].T)
+    """Dense (nz, ny, nx, Q) -> site-ordered (Q, n)."""
+    q = f_dense.shape[-1]
+    return np.ascontiguousarray(f_dense.reshape(-1, q)[inputs.pore_sites(mask)].T)
 
 
 def rel_err(a, b):

@@ -1,0 +1,198 @@
+"""Parity of the HIP two-fluid colour-gradient path with the FP64 oracle.
+
+Per step: FP64 storage <= 1e-12, FP32 <= 1e-6 of max |value| for f, A and B.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1806_10589_amd import fluxlbm, inputs
+
+from .gpu_helpers import dense_to_sites, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+W7 = np.array([1 / 3] + [1 / 9] * 6)
+
+
+def colour_pair(mask, *, precision, tau=0.9, alpha=0.01, beta=0.7, phi_solid=-0.5, q_target=0.0,
+                periodic_x=True, periodic_y=True, z_mode=0, watchdog_every=1000):
+    lat = fluxlbm.Lattice(mask, tau=tau, q_target=q_target, precision=precision, model="colour",
+                          periodic_x=periodic_x, periodic_y=periodic_y, z_mode=z_mode,
+                          alpha=alpha, beta=beta, phi_solid=phi_solid, watchdog_every=watchdog_every)
+    orc = oracle.OracleColour(mask, tau=tau, alpha=alpha, beta=beta, phi_solid=phi_solid,
+                              q_target=q_target, periodic_x=periodic_x, periodic_y=periodic_y,
+                              z_mode=z_mode)
+    return lat, orc
+
+
+def random_colour_state(mask, seed):
+    _, _, _, w, _ = oracle.velocity_set()
+    rng = np.random.default_rng(seed)
+    f = w * (1.0 + 0.05 * rng.uniform(-1, 1, mask.shape + (19,)))
+    na = rng.uniform(0.0, 1.0, mask.shape)
+    nb = 1.0 - na + 0.02 * rng.uniform(-1, 1, mask.shape)
+    A = W7 * na[..., None] * (1.0 + 0.05 * rng.uniform(-1, 1, mask.shape + (7,)))
+    B = W7 * nb[..., None] * (1.0 + 0.05 * rng.uniform(-1, 1, mask.shape + (7,)))
+    solid = mask.astype(bool)
+    f[solid] = 0
+    A[solid] = 0
+    B[solid] = 0
+    return f, A, B
+
+
+def load_colour_state(lat, orc, mask, seed):
+    f, A, B = random_colour_state(mask, seed)
+    orc.set_state(f, A, B)
+    lat.write_distributions(dense_to_sites(mask, f))
+    lat.write_colour(dense_to_sites(mask, A), dense_to_sites(mask, B))
+    return f, A, B
+
+
+def compare(lat, orc, mask):
+    f, A, B = orc.get_state()
+    ef = rel_err(lat.read_distributions(), dense_to_sites(mask, f))
+    Ag, Bg = lat.read_colour()
+    ea = rel_err(Ag, dense_to_sites(mask, A))
+    eb = rel_err(Bg, dense_to_sites(mask, B))
+    return ef, ea, eb
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("z_mode,px,py", [(1, 1, 1), (2, 0, 1)])
+def test_colour_one_step_closed_box(precision, z_mode, px, py):
+    mask = inputs.random_mask((9, 11, 13), 0.25, 201)
+    lat, orc = colour_pair(mask, precision=precision, periodic_x=px, periodic_y=py, z_mode=z_mode)
+    load_colour_state(lat, orc, mask, 202)
+    lat.step(1)
+    orc.step(1)
+    assert max(compare(lat, orc, mask)) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape,px,py", [((10, 12, 11), 1, 0), ((6, 5, 4), 1, 1), ((20, 34, 30), 1, 1)])
+def test_colour_one_step_flux_box(precision, shape, px, py):
+    mask = inputs.random_mask(shape, 0.25, 211)
+    mask[0, 0, 0] = 0
+    lat, orc = colour_pair(mask, precision=precision, q_target=0.002 * shape[1] * shape[2],
+                           periodic_x=px, periodic_y=py)
+    load_colour_state(lat, orc, mask, 212)
+    lat.step(1)
+    h_orc = orc.step(1)
+    assert max(compare(lat, orc, mask)) <= TOL[precision]
+    h = lat.history(1)
+    assert abs(h[0, 1] - h_orc[0, 1]) <= 1e-12 * max(1.0, abs(h_orc[0, 1]))
+
+
+def test_colour_streaming_only_is_exact():
+    mask = inputs.random_mask((7, 6, 8), 0.3, 221)
+    mask[0, 0, 0] = 0
+    lat, orc = colour_pair(mask, precision="fp64", periodic_x=True, periodic_y=False, z_mode=2)
+    lat.set_collision(False)
+    orc.set_collision(False)
+    load_colour_state(lat, orc, mask, 222)
+    lat.step(1)
+    orc.step(1)
+    _, A, B = orc.get_state()
+    Ag, Bg = lat.read_colour()
+    assert np.array_equal(Ag, dense_to_sites(mask, A))
+    assert np.array_equal(Bg, dense_to_sites(mask, B))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_colour_drainage_many_steps(precision):
+    """Non-wetting injection into a wetting-filled porous box: 120 steps."""
+    mask = inputs.random_mask((24, 14, 16), 0.2, 231)
+    mask[:4] = 0
+    q = 0.003 * 14 * 16
+    lat, orc = colour_pair(mask, precision=precision, tau=1.0, alpha=0.005, beta=0.7, phi_solid=-0.7,
+                           q_target=q, watchdog_every=40)
+    na = np.zeros(mask.shape)
+    na[:4] = 1.0
+    nb = 1.0 - na
+    na[mask.astype(bool)] = 0
+    nb[mask.astype(bool)] = 0
+    orc.init(na, nb)
+    sites = inputs.pore_sites(mask)
+    lat.init_colour(na.reshape(-1)[sites], nb.reshape(-1)[sites])
+    n = 120
+    lat.step(n)
+    h_orc = orc.step(n)
+    assert lat.sync() == fluxlbm.FLBM_OK
+    h = lat.history(n)
+    ef, ea, eb = compare(lat, orc, mask)
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    assert max(ef, ea, eb) <= tol
+    assert np.abs(h[:, 1] - q).max() <= (1e-12 if precision == "fp64" else 1e-6 * q)
+    rec = ~np.isnan(h[:, 5])
+    assert rec[39] and rec[79] and rec[-1]
+    rtol = 1e-10 if precision == "fp64" else 1e-5
+    assert np.abs(h[rec, 5] - h_orc[rec, 5]).max() <= rtol * h_orc[0, 5]
+    assert np.abs(h[rec, 6] - h_orc[rec, 6]).max() <= rtol * h_orc[0, 6]
+    phi = lat.phase()
+    _, _, _, _, phi_o = orc.fields()
+    assert np.abs(phi - phi_o.reshape(-1)[sites]).max() <= (1e-10 if precision == "fp64" else 1e-4)
+
+
+def test_colour_conserved_closed_box_gpu():
+    mask = inputs.random_mask((16, 12, 14), 0.2, 241)
+    lat, orc = colour_pair(mask, precision="fp64", z_mode=1, watchdog_every=50)
+    f, A, B = load_colour_state(lat, orc, mask, 242)
+    lat.step(200)
+    h = lat.history(200)
+    rec = ~np.isnan(h[:, 5])
+    assert np.abs(h[rec, 5] - A.sum()).max() < 1e-11 * A.sum()
+    assert np.abs(h[rec, 6] - B.sum()).max() < 1e-11 * B.sum()
+
+
+def test_colour_checkpoint_resume_is_bitwise():
+    mask = inputs.random_mask((10, 9, 8), 0.2, 251)
+    mask[0] = 0
+    lat, _ = colour_pair(mask, precision="fp32", q_target=0.05)
+    sites = inputs.pore_sites(mask)
+    na = np.zeros(mask.shape)
+    na[:3] = 1
+    lat.init_colour(na.reshape(-1)[sites], 1.0 - na.reshape(-1)[sites])
+    lat.step(30)
+    blob = lat.save_state()
+    lat.step(30)
+    f1 = lat.read_distributions()
+    A1, B1 = lat.read_colour()
+    lat.load_state(blob)
+    lat.step(30)
+    f2 = lat.read_distributions()
+    A2, B2 = lat.read_colour()
+    assert np.array_equal(f1, f2) and np.array_equal(A1, A2) and np.array_equal(B1, B2)
+
+
+@pytest.fixture(scope="module")
+def crop64():
+    """64^3 crop of the 384^3 sphere pack (seed 3, porosity 0.30) with the
+    non-wetting reservoir at the inlet and a wetting reservoir at the outlet."""
+    mask, phi, _ = inputs.sphere_pack(384, 0.30, seed=3)
+    crop = inputs.carve_reservoirs(mask[:64, :64, :64], 6)
+    return crop
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_colour_crop64_parity(crop64, precision):
+    mask = crop64
+    gamma_ca = 1e-5 * 0.01 * 0.30 * 64 * 64 / (1.0 / 6.0)  # Q* = Ca gamma eps A / mu_w
+    lat, orc = colour_pair(mask, precision=precision, tau=1.0, alpha=0.01, beta=0.7,
+                           phi_solid=-0.7071, q_target=gamma_ca, watchdog_every=50)
+    na = np.zeros(mask.shape)
+    na[:6] = 1.0
+    nb = 1.0 - na
+    na[mask.astype(bool)] = 0
+    nb[mask.astype(bool)] = 0
+    orc.init(na, nb)
+    sites = inputs.pore_sites(mask)
+    lat.init_colour(na.reshape(-1)[sites], nb.reshape(-1)[sites])
+    lat.step(1)
+    orc.step(1)
+    assert max(compare(lat, orc, mask)) <= TOL[precision]
+    lat.step(99)
+    orc.step(99, record=False)
+    ef, ea, eb = compare(lat, orc, mask)
+    assert max(ef, ea, eb) <= (1e-10 if precision == "fp64" else 1e-4)
