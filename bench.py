@@ -29,6 +29,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in
 CONFIGS = {
     # name: (builder, lattice kwargs, description)
     "pack256": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp32"),
+    "pack256h": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp16dev"),
     "pack512": dict(n=512, porosity=0.25, seed=5, reservoir=6, tau=0.8, darcy=1e-5, precision="fp32"),
     "slit": dict(slit=True, tau=1.0, q=0.5, precision="fp64"),
 }

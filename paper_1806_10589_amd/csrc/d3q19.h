@@ -80,6 +80,12 @@ FLBM_HD constexpr int mb_norm2(int k)
     return s;
 }
 
+// FP16 storage of deviations: h_q = (f_q - w_q) 2^half_shift(q), a power of
+// two per weight class, so that deviations up to about 1.5 w_q (rest) and
+// 2.25 w_q (moving directions) stay below the FP16 maximum and small ones stay
+// out of its subnormal range; scaling by a power of two is exact.
+FLBM_HD constexpr int half_shift(int q) { return q == 0 ? 17 : (q <= 6 ? 19 : 20); }
+
 // D3Q7 mass transport (Appendix A): velocities q = 0..6 of the set above,
 // weights 1/3 and 1/9.
 constexpr int Q7 = 7;

@@ -100,6 +100,30 @@ flbm_status fail(flbm_ctx *c, flbm_status code, const std::string &msg)
 
 bool is_fp64(const flbm_ctx *c) { return c->p.precision == FLBM_FP64; }
 
+// Call fn(T{}) with T the storage type of the distributions.
+template <typename Fn>
+void with_storage(const flbm_ctx *c, Fn &&fn)
+{
+    if (c->p.precision == FLBM_FP64)
+        fn(double{});
+    else if (c->p.precision == FLBM_FP16DEV)
+        fn(_Float16{});
+    else
+        fn(float{});
+}
+
+// Host-side codec of the stored deviations (the device codec's mirror).
+template <typename T> double host_dec(T v, int) { return (double)v; }
+template <typename T> T host_enc(double g, int) { return (T)g; }
+template <> double host_dec<_Float16>(_Float16 v, int q)
+{
+    return (double)v / (double)(1u << d3q19::half_shift(q));
+}
+template <> _Float16 host_enc<_Float16>(double g, int q)
+{
+    return (_Float16)(float)(g * (double)(1u << d3q19::half_shift(q)));
+}
+
 size_t f_bytes(const flbm_ctx *c) { return (size_t)(19 * c->lat.n_pad + SENT_PAD) * c->elem; }
 
 // Carve the device slab. With base == nullptr only the size is computed.
@@ -313,10 +337,7 @@ void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
         if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
         return;
     }
-    if (is_fp64(c))
-        launch_step<double>(c, s, from, obs);
-    else
-        launch_step<float>(c, s, from, obs);
+    with_storage(c, [&](auto tag) { launch_step<decltype(tag)>(c, s, from, obs); });
 }
 
 void drop_graphs(flbm_ctx *c)
@@ -350,12 +371,11 @@ flbm_status capture_graph(flbm_ctx *c, int parity)
 flbm_status refresh_inlet_sum(flbm_ctx *c)
 {
     if (!c->need_plane || c->p.z_mode != FLBM_Z_FLUX) return FLBM_OK;
-    if (is_fp64(c))
-        hipLaunchKernelGGL(k_inlet_plane<double>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
-                           (const double *)c->f[c->cur], c->nbr, plane_args(c, c->cur));
-    else
-        hipLaunchKernelGGL(k_inlet_plane<float>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
-                           (const float *)c->f[c->cur], c->nbr, plane_args(c, c->cur));
+    with_storage(c, [&](auto tag) {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_inlet_plane<T>, dim3(c->plane_blocks), dim3(BLOCK), 0, c->stream,
+                           (const T *)c->f[c->cur], c->nbr, plane_args(c, c->cur));
+    });
     HIPCHK(c, hipGetLastError());
     c->need_plane = false;
     return FLBM_OK;
@@ -394,12 +414,8 @@ flbm_status fill_equilibrium(flbm_ctx *c, double rho, double ux, double uy, doub
         dev.v[q] = d3q19::weight(q) * ((rho - 1.0) + c->p.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
     }
     Dev19 zero{};
-    for (int w = 0; w < 2; ++w) {
-        if (is_fp64(c))
-            launch_fill<double>(c, w, w == c->cur ? dev : zero);
-        else
-            launch_fill<float>(c, w, w == c->cur ? dev : zero);
-    }
+    for (int w = 0; w < 2; ++w)
+        with_storage(c, [&](auto tag) { launch_fill<decltype(tag)>(c, w, w == c->cur ? dev : zero); });
     HIPCHK(c, hipGetLastError());
     return reset_state(c);
 }
@@ -446,8 +462,10 @@ flbm_status check_params(const flbm_params *p, std::string &why)
     if (!(p->tau > 0.5)) return why = "tau must exceed 1/2", FLBM_EINVAL;
     if (!(p->rho0 > 0.0)) return why = "rho0 must be positive", FLBM_EINVAL;
     if (p->z_mode < FLBM_Z_FLUX || p->z_mode > FLBM_Z_WALL) return why = "unknown z_mode", FLBM_EINVAL;
-    if (p->precision != FLBM_FP64 && p->precision != FLBM_FP32)
-        return why = "precision not available", FLBM_EINVAL;
+    if (p->precision != FLBM_FP64 && p->precision != FLBM_FP32 && p->precision != FLBM_FP16DEV)
+        return why = "unknown precision", FLBM_EINVAL;
+    if (p->model == FLBM_COLOUR && p->precision == FLBM_FP16DEV)
+        return why = "the colour model stores FP32 or FP64", FLBM_EINVAL;
     if (p->model != FLBM_BGK && p->model != FLBM_COLOUR) return why = "unknown model", FLBM_EINVAL;
     if (p->model == FLBM_COLOUR && (!std::isfinite(p->alpha) || !std::isfinite(p->beta) ||
                                     !std::isfinite(p->phi_solid)))
@@ -502,7 +520,7 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
     c->spec.z_mode = p->z_mode;
     c->spec.reservoir_layers = p->reservoir_layers;
     c->stream = (hipStream_t)hip_stream;
-    c->elem = is_fp64(c) ? 8 : 4;
+    c->elem = p->precision == FLBM_FP64 ? 8 : (p->precision == FLBM_FP16DEV ? 2 : 4);
     c->colour = p->model == FLBM_COLOUR;
     int code = FLBM_OK;
     std::string e = build_lattice(solid_mask, c->spec, c->lat, code);
@@ -915,12 +933,11 @@ flbm_status flbm_read_fields(flbm_ctx *c, double *rho, double *ux, double *uy, d
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
-    if (is_fp64(c))
-        hipLaunchKernelGGL(k_moments<double>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
-                           (const double *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
-    else
-        hipLaunchKernelGGL(k_moments<float>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
-                           (const float *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
+    with_storage(c, [&](auto tag) {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_moments<T>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
+                           (const T *)c->f[c->cur], n, npad, 1.0 / c->p.rho0, c->fields);
+    });
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double *dst[4] = {rho, ux, uy, uz};
@@ -936,17 +953,16 @@ flbm_status flbm_read_distributions(flbm_ctx *c, double *f)
     if (rc) return rc;
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (is_fp64(c)) {
-        std::vector<double> h((size_t)19 * npad);
-        HIPCHK(c, hipMemcpy(h.data(), c->f[c->cur], h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    hipError_t e = hipSuccess;
+    with_storage(c, [&](auto tag) {
+        using T = decltype(tag);
+        std::vector<T> h((size_t)19 * npad);
+        e = hipMemcpy(h.data(), c->f[c->cur], h.size() * sizeof(T), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return;
         for (int q = 0; q < 19; ++q)
-            for (int64_t s = 0; s < n; ++s) f[q * n + s] = d3q19::weight(q) + h[q * npad + s];
-    } else {
-        std::vector<float> h((size_t)19 * npad);
-        HIPCHK(c, hipMemcpy(h.data(), c->f[c->cur], h.size() * sizeof(float), hipMemcpyDeviceToHost));
-        for (int q = 0; q < 19; ++q)
-            for (int64_t s = 0; s < n; ++s) f[q * n + s] = d3q19::weight(q) + (double)h[q * npad + s];
-    }
+            for (int64_t s = 0; s < n; ++s) f[q * n + s] = d3q19::weight(q) + host_dec<T>(h[q * npad + s], q);
+    });
+    HIPCHK(c, e);
     return FLBM_OK;
 }
 
@@ -957,17 +973,15 @@ flbm_status flbm_write_distributions(flbm_ctx *c, const double *f)
     if (rc) return rc;
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (is_fp64(c)) {
-        std::vector<double> h((size_t)19 * npad, 0.0);
+    hipError_t e = hipSuccess;
+    with_storage(c, [&](auto tag) {
+        using T = decltype(tag);
+        std::vector<T> h((size_t)19 * npad, (T)0);
         for (int q = 0; q < 19; ++q)
-            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = f[q * n + s] - d3q19::weight(q);
-        HIPCHK(c, hipMemcpy(c->f[c->cur], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
-    } else {
-        std::vector<float> h((size_t)19 * npad, 0.0f);
-        for (int q = 0; q < 19; ++q)
-            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = (float)(f[q * n + s] - d3q19::weight(q));
-        HIPCHK(c, hipMemcpy(c->f[c->cur], h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
-    }
+            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = host_enc<T>(f[q * n + s] - d3q19::weight(q), q);
+        e = hipMemcpy(c->f[c->cur], h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    });
+    HIPCHK(c, e);
     return reset_state(c);
 }
 
@@ -976,14 +990,12 @@ flbm_status flbm_get_observables(flbm_ctx *c, double *mass, double *umax, int32_
     if (!c) return FLBM_EINVAL;
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
-    if (is_fp64(c))
-        hipLaunchKernelGGL(k_state_observables<double>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
-                           (const double *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
+    with_storage(c, [&](auto tag) {
+        using T = decltype(tag);
+        hipLaunchKernelGGL(k_state_observables<T>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
+                           (const T *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
                            c->obs_umax2, c->obs_bad);
-    else
-        hipLaunchKernelGGL(k_state_observables<float>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
-                           (const float *)c->f[c->cur], c->lat.n_pad, 1.0 / c->p.rho0, c->obs_mass,
-                           c->obs_umax2, c->obs_bad);
+    });
     hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, c->stream, obs_args(c, 0, c->blocks256));
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1026,10 +1038,10 @@ flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, doubl
     for (int32_t i = 0; i < n; ++i) {
         const int from = c->cur;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
-        if (is_fp64(c))
-            launch_stream_collide<double>(c, c->stream, (const double *)c->f[from], (double *)c->f[from ^ 1], false);
-        else
-            launch_stream_collide<float>(c, c->stream, (const float *)c->f[from], (float *)c->f[from ^ 1], false);
+        with_storage(c, [&](auto tag) {
+            using T = decltype(tag);
+            launch_stream_collide<T>(c, c->stream, (const T *)c->f[from], (T *)c->f[from ^ 1], false);
+        });
         HIPCHK(c, hipEventRecord(ev[1], c->stream));
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipEventSynchronize(ev[1]));

@@ -94,9 +94,27 @@ struct PlaneArgs {
     double *kpart;
 };
 
-template <typename T> struct Compute;
-template <> struct Compute<float> { using type = float; };
-template <> struct Compute<double> { using type = double; };
+// Storage codec: how a stored population of direction q becomes the
+// arithmetic value (the deviation g_q = f_q - w_q) and back. FP32 and FP64
+// store g directly; FP16 stores g 2^half_shift(q) (exact power-of-two
+// scaling, arithmetic in FP32, rounding to nearest even on store).
+template <typename T> struct Codec {
+    typedef T R;
+    static __device__ __forceinline__ R dec(T v, int) { return v; }
+    static __device__ __forceinline__ T enc(R v, int) { return v; }
+};
+template <> struct Codec<_Float16> {
+    typedef float R;
+    static __device__ __forceinline__ float dec(_Float16 v, int q)
+    {
+        return (float)v * (1.0f / (float)(1u << d3q19::half_shift(q)));
+    }
+    static __device__ __forceinline__ _Float16 enc(float v, int q)
+    {
+        return (_Float16)(v * (float)(1u << d3q19::half_shift(q)));
+    }
+};
+template <typename T> struct Compute { using type = typename Codec<T>::R; };
 
 typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -120,6 +138,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint3
 }
 
 template <int BYTES> struct RawBits;
+template <> struct RawBits<2> { typedef uint16_t type; };
 template <> struct RawBits<4> { typedef uint32_t type; };
 template <> struct RawBits<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
 template <> struct RawBits<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
@@ -128,7 +147,9 @@ template <int BYTES, int AUX = 0>
 __device__ __forceinline__ typename RawBits<BYTES>::type buf_load_raw(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                                                       uint32_t soff)
 {
-    if constexpr (BYTES == 4)
+    if constexpr (BYTES == 2)
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX);
+    else if constexpr (BYTES == 4)
         return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX);
     else if constexpr (BYTES == 8)
         return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX);
@@ -142,7 +163,9 @@ __device__ __forceinline__ void buf_store_raw_nt(typename RawBits<BYTES>::type v
                                                  uint32_t voff, uint32_t soff)
 {
     constexpr int aux = SC_NT ? 2 : 0;
-    if constexpr (BYTES == 4)
+    if constexpr (BYTES == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)voff, (int)soff, aux);
+    else if constexpr (BYTES == 4)
         __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)voff, (int)soff, aux);
     else if constexpr (BYTES == 8)
         __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)voff, (int)soff, aux);
@@ -402,11 +425,12 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
     double k = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x; i < a.a_in;
          i += (int64_t)gridDim.x * BLOCK) {
-        double ki = (double)fin[i];
+        double ki = (double)Codec<T>::dec(fin[i], 0);
 #pragma unroll
         for (int q = 1; q < 19; ++q)
             if (d3q19::inlet_coeff(q))
-                ki += d3q19::inlet_coeff(q) * (double)fin[nbr[(int64_t)(q - 1) * a.npad + i]];
+                ki += d3q19::inlet_coeff(q) *
+                      (double)Codec<T>::dec(fin[nbr[(int64_t)(q - 1) * a.npad + i]], q);
         k += ki;
     }
     k = block_sum<BLOCK>(k, lds);
@@ -551,10 +575,10 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
         const uint32_t vo = (uint32_t)s0 * (uint32_t)sizeof(T);
         const uint32_t vi = (uint32_t)s0 * 4u;
         {
-            R r[V];
-            buf_load_v<V, T>(rf, vo, 0u, r);
+            T r[V];
+            buf_load_v<V, T, T>(rf, vo, 0u, r);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v][0] = r[v];
+            for (int v = 0; v < V; ++v) g[v][0] = Codec<T>::dec(r[v], 0);
         }
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
@@ -562,24 +586,24 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
             buf_load_v<V, int32_t, int32_t, SC_IDX_AUX>(rn, vi, (uint32_t)(q - 1) * (uint32_t)npad * 4u, idx);
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                R r[1];
-                buf_load_v<1, T>(rf, (uint32_t)idx[v] * (uint32_t)sizeof(T), 0u, r);
-                g[v][q] = r[0];
+                T r[1];
+                buf_load_v<1, T, T>(rf, (uint32_t)idx[v] * (uint32_t)sizeof(T), 0u, r);
+                g[v][q] = Codec<T>::dec(r[0], q);
             }
         }
     } else {
         {
-            R r[V];
+            T r[V];
             load_v<V>(fin + s0, r);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v][0] = r[v];
+            for (int v = 0; v < V; ++v) g[v][0] = Codec<T>::dec(r[v], 0);
         }
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
             int32_t idx[V];
             load_v<V>(nbr + (int64_t)(q - 1) * npad + s0, idx);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v][q] = (R)fin[idx[v]];
+            for (int v = 0; v < V; ++v) g[v][q] = Codec<T>::dec(fin[idx[v]], q);
         }
     }
 
@@ -614,7 +638,9 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
 
     // Contribution of this tile's post-collision populations to the next
     // step's inlet sum: the pull table is a bijection, so each population of
-    // planes 0-1 that an inlet site will pull carries one fixed weight.
+    // planes 0-1 that an inlet site will pull carries one fixed weight. The
+    // sum is taken over the values exactly as stored (encoded and decoded),
+    // so that it equals what the next step's inlet sites will read.
     double s_next = 0.0;
     if (tile < a.nt01) {
 #pragma unroll
@@ -624,7 +650,7 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
 #pragma unroll
                 for (int q = 0; q < 19; ++q) {
                     const uint32_t c = (uint32_t)(cw >> (2 * q)) & 3u;
-                    if (c) s_next += (double)c * (double)g[v][q];
+                    if (c) s_next += (double)c * (double)Codec<T>::dec(Codec<T>::enc(g[v][q], q), q);
                 }
             }
     }
@@ -634,17 +660,17 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
         const uint32_t vo = (uint32_t)s0 * (uint32_t)sizeof(T);
 #pragma unroll
         for (int q = 0; q < 19; ++q) {
-            R out[V];
+            T out[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) out[v] = g[v][q];
+            for (int v = 0; v < V; ++v) out[v] = Codec<T>::enc(g[v][q], q);
             buf_store_v_nt<V, T>(ro, vo, (uint32_t)q * (uint32_t)npad * (uint32_t)sizeof(T), out);
         }
     } else {
 #pragma unroll
         for (int q = 0; q < 19; ++q) {
-            R out[V];
+            T out[V];
 #pragma unroll
-            for (int v = 0; v < V; ++v) out[v] = g[v][q];
+            for (int v = 0; v < V; ++v) out[v] = Codec<T>::enc(g[v][q], q);
             store_v_nt<V>(fout + (int64_t)q * npad + s0, out);
         }
     }
@@ -741,7 +767,7 @@ __global__ __launch_bounds__(BLOCK) void k_state_observables(const T *__restrict
     double d = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
-        const double v = (double)f[(int64_t)q * npad + s];
+        const double v = (double)Codec<T>::dec(f[(int64_t)q * npad + s], q);
         d += v;
         jx += d3q19::cx[q] * v;
         jy += d3q19::cy[q] * v;
@@ -780,7 +806,7 @@ __global__ __launch_bounds__(BLOCK) void k_moments(const T *__restrict__ f, int6
     double d = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
-        const double v = (double)f[(int64_t)q * npad + s];
+        const double v = (double)Codec<T>::dec(f[(int64_t)q * npad + s], q);
         d += v;
         jx += d3q19::cx[q] * v;
         jy += d3q19::cy[q] * v;
@@ -811,7 +837,7 @@ __global__ __launch_bounds__(BLOCK) void k_fill(T *__restrict__ f, int64_t n, in
 #pragma unroll
             for (int k = 0; k < 19; ++k)
                 if (k == q) x = dev.v[k];
-            v = (T)x;
+            v = Codec<T>::enc((typename Codec<T>::R)x, (int)q);
         }
         f[i] = v;
     }

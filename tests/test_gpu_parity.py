@@ -187,3 +187,44 @@ def test_large_inlet_plane_grid_stride():
     assert abs(h[0, 0] - h_orc[0, 0]) <= 1e-13
     assert abs(h[0, 1] - 100.0) <= 1e-9
     assert _compare(lat, orc, mask) <= 1e-12
+
+
+# ---------------------------------------------------------------- FP16 deviation storage
+
+def test_fp16dev_one_step_flux_box():
+    """FP16 storage of scaled deviations: one step from a random state. Each
+    stored deviation (|g| <= 0.05 w) is rounded to 11 significant bits on
+    load and on store: error bound ~1.2e-5 of max |f| per rounding."""
+    mask = inputs.random_mask((12, 14, 13), 0.3, 71)
+    mask[0, 0, 0] = 0
+    lat, orc = pair(mask, precision="fp16dev", tau=0.9, q_target=0.3, periodic_x=True, periodic_y=False)
+    load_same_state(lat, orc, mask, 72)
+    lat.step(1)
+    h_orc = orc.step(1)
+    err = _compare(lat, orc, mask)
+    assert err <= 5e-5, err
+    h = lat.history(1)
+    assert abs(h[0, 1] - 0.3) <= 1e-12
+    assert abs(h[0, 0] - h_orc[0, 0]) <= 1e-5
+
+
+def test_fp16dev_slit_channel_against_oracle():
+    """Error of the FP16-deviation mode against the FP64 oracle on the slit
+    after 2000 steps (reported in the assertion message)."""
+    mask = inputs.slit_channel(16, 16, 64)
+    lat, orc = pair(mask, precision="fp16dev", tau=1.0, q_target=0.5, periodic_x=False, periodic_y=True)
+    lat.init_equilibrium(1.0)
+    orc.init_equilibrium(1.0)
+    lat.step(2000)
+    h_orc = orc.step(2000)
+    h = lat.history(2000)
+    assert lat.sync() == fluxlbm.FLBM_OK
+    rho, ux, uy, uz = lat.fields()
+    _, _, _, uz_o = orc.fields()
+    sites = inputs.pore_sites(mask)
+    ref = uz_o.reshape(-1)[sites]
+    err_u = np.abs(uz - ref).max() / np.abs(ref).max()
+    assert err_u <= 1e-2, f"u_z error {err_u:.3e}"
+    assert np.abs(h[:, 1] - 0.5).max() <= 1e-12
+    q_err = abs(0.5 * (h[-1, 2] + h[-2, 2]) - 0.5 * (h_orc[-1, 2] + h_orc[-2, 2])) / 0.5
+    assert q_err <= 1e-2, f"outlet flux error {q_err:.3e}"
