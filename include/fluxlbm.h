@@ -181,6 +181,80 @@ flbm_status flbm_read_fields(flbm_ctx *c, double *rho, double *ux, double *uy, d
 flbm_status flbm_read_distributions(flbm_ctx *c, double *f);
 flbm_status flbm_write_distributions(flbm_ctx *c, const double *f);
 
+/* ---------------------------------------------------------------------
+ * Learned inlet controller (a learned addition on top of the method: the
+ * paper's plain update of eq. potential stays its fallback and judge).
+ *
+ * flbm_mlp is a 32 -> 128 -> 128 -> 1 multilayer perceptron with tanh
+ * hidden layers whose products run on the matrix cores with BF16 operands
+ * and FP32 accumulation; FP32 master weights, mean-squared-error loss, Adam.
+ * Parameter order (FP32): W1 [128][32], b1 [128], W2 [128][128], b2 [128],
+ * W3 [1][128], b3 [1] (flbm_mlp_num_params). Inputs are device FP32 arrays
+ * [batch][32], targets and outputs device FP32 [batch]; work goes to the
+ * stream given at creation. */
+typedef struct flbm_mlp flbm_mlp;
+flbm_status flbm_mlp_create(int32_t max_batch, void *hip_stream, flbm_mlp **out);
+flbm_status flbm_mlp_destroy(flbm_mlp *m);
+flbm_status flbm_mlp_num_params(int32_t *n);
+/* host FP32 parameters; setting them also resets the optimiser state */
+flbm_status flbm_mlp_set_params(flbm_mlp *m, const float *host, int32_t n);
+flbm_status flbm_mlp_get_params(flbm_mlp *m, float *host, int32_t n);
+flbm_status flbm_mlp_forward(flbm_mlp *m, const float *dev_x, float *dev_y, int32_t batch);
+/* loss and its gradient with respect to every parameter (host FP32), for checks */
+flbm_status flbm_mlp_gradients(flbm_mlp *m, const float *dev_x, const float *dev_t, int32_t batch,
+                               float *host_grads, float *host_loss);
+/* one Adam step (beta 0.9, 0.999, eps 1e-8) at learning rate lr; host_loss
+ * may be NULL (then the call does not synchronise) */
+flbm_status flbm_mlp_train_step(flbm_mlp *m, const float *dev_x, const float *dev_t, int32_t batch, float lr,
+                                float *host_loss);
+/* C = A B with A (M x K) element (i,k) at A[i*a_rs + k*a_cs], B (K x N)
+ * element (k,j) at B[k*b_rs + j*b_cs], C[i*c_rs + j]; FP32 arrays on the
+ * device, operands rounded to BF16, FP32 accumulation (the network's matrix
+ * core routine, exposed for testing). Asynchronous on hip_stream. */
+flbm_status flbm_gemm_bf16(const float *A, int64_t a_rs, int64_t a_cs, const float *B, int64_t b_rs,
+                           int64_t b_cs, float *C, int64_t c_rs, int32_t M, int32_t N, int32_t K,
+                           void *hip_stream);
+
+typedef struct flbm_controller_params {
+    float geometry[15];   /* static inputs 0..14 of the network (sample and inlet-slice statistics) */
+    float reserved;
+    double drho_ref;      /* reference inlet-outlet density difference (input 31, proposal) */
+    double gain;          /* fraction of the step from the plain density to the proposal taken */
+    double trust0;        /* initial bound on |Q_in - Q*| / Q* that a proposal may cause */
+    double release_tol;   /* two-step mean |Q_out - Q*| / Q* that returns control to the
+                             plain update for good */
+    int32_t trust_steps;  /* the bound decays linearly to zero over this many steps */
+    int32_t reserved2;
+} flbm_controller_params;
+
+/* Attach (net != NULL) or detach (net == NULL) the controller. While
+ * attached, after every step the network reads 32 inputs: the 15 geometry
+ * values, the outlet-flux errors (Qbar_out - Q*) / |Q*| clipped to [-2, 2]
+ * at the lags 1, 2, 3, 6, 11, 20, 36, 65, 119, 215, 391, 710, 1290, 2345,
+ * 4260, 7740 steps back (Qbar the mean of two consecutive steps, 0 before
+ * the first step), and log10(drho / drho_ref) / 3 clipped to [-1, 1] (-1 if
+ * drho <= 0), drho = rho_in - rho_out of the last step. Its output r,
+ * clipped to [-4, 4], is the predicted steady density difference as
+ * log(drho_inf / drho_ref): the proposal is rho_hat = rho_out + drho_ref exp(r).
+ * The next step uses
+ *   rho_in = rho_plain + clip(gain (rho_hat - rho_plain), +-bound rho0 |Q*| / A)
+ * with rho_plain the update of eq. potential and bound = trust0 (1 -
+ * n / trust_steps)^+ after n decisions, i.e. |Q_in - Q*| / Q* <= bound. No
+ * offset once the two-step mean outlet error has met release_tol (sticky),
+ * when Q* <= 0, or when the proposal is not finite. With trust0 = 0 the
+ * run is the plain method exactly (the inputs are still recorded). The
+ * network must outlive the attachment. Flux mode only (else FLBM_ESTATE).
+ * Synchronises. */
+flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_controller_params *p);
+/* attached flag, released flag, last offset, decisions taken (synchronises) */
+flbm_status flbm_controller_state(flbm_ctx *c, int32_t *active, int32_t *released, double *delta,
+                                  int64_t *decisions);
+/* The controller's last n decisions, oldest first (n <= flbm_history_capacity,
+ * and decisions taken since the attachment): inputs x[n][32] (FP32) and
+ * aux[n][4] = {drho, rho_plain, r, offset} (FP64), decision k taken after
+ * step k. Synchronises. */
+flbm_status flbm_controller_trace(flbm_ctx *c, int32_t n, float *x, double *aux);
+
 /* Two-fluid colour model (Appendix A; FLBM_COLOUR contexts only, else
  * FLBM_ESTATE). The colours A (non-wetting) and B (wetting) are D3Q7
  * distributions over the velocities q = 0..6 with weights 1/3, 1/9.

@@ -95,6 +95,7 @@ typedef struct orc_lattice {
     int nx, ny, nz;
     int periodic_x, periodic_y, z_mode;
     double tau, rho0, q_target, rho_out;
+    double rho_offset;    /* added to the inlet density of eq. potential (controller tests) */
     int collide;
     long ncell;
     unsigned char *solid; /* [nz][ny][nx], 1 = solid */
@@ -426,7 +427,7 @@ static void apply_momentum_bc(orc_lattice *L, double *uz_in, double *uz_out, dou
                 if (L->solid[c]) continue;
                 ksum += inlet_known_sum(&L->ft[c * Q19]);
             }
-        rho_in = rho0 * L->q_target / (double)L->a_in + ksum / (double)L->a_in;
+        rho_in = rho0 * L->q_target / (double)L->a_in + ksum / (double)L->a_in + L->rho_offset;
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
                 long c = cell_index(L, x, y, 0);
@@ -510,6 +511,26 @@ static int step_once(orc_lattice *L, double *hist)
     L->ft = t;
     L->step++;
     return bad ? -1 : 0;
+}
+
+/* An offset added to the inlet density of eq. potential in every following
+ * step (0 for the paper's method; the tests of the inlet controller use it). */
+void orc_set_inlet_offset(orc_lattice *L, double d) { L->rho_offset = d; }
+
+/* The inlet density eq. potential gives for the next step, without the
+ * offset: stream the current state (into the scratch buffer, which the next
+ * step overwrites anyway) and sum K_i over the inlet pore sites. */
+double orc_plain_inlet_density(orc_lattice *L)
+{
+    stream_push(L);
+    double ksum = 0.0;
+    for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x) {
+            long c = cell_index(L, x, y, 0);
+            if (L->solid[c]) continue;
+            ksum += inlet_known_sum(&L->ft[c * Q19]);
+        }
+    return (L->rho0 * L->q_target + ksum) / (double)L->a_in;
 }
 
 /* Advance n steps; hist (may be NULL) gets 5 values per step. */

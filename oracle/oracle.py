@@ -56,6 +56,9 @@ def _load():
         lib.orc_set_collision.argtypes = [_p, _i]
         lib.orc_set_target_flux.argtypes = [_p, _d]
         lib.orc_set_outlet_density.argtypes = [_p, _d]
+        lib.orc_set_inlet_offset.argtypes = [_p, _d]
+        lib.orc_plain_inlet_density.argtypes = [_p]
+        lib.orc_plain_inlet_density.restype = _d
         lib.orc_step_count.argtypes = [_p]
         lib.orc_step_count.restype = ctypes.c_long
         lib.orc_inlet_area.argtypes = [_p]
@@ -208,6 +211,14 @@ class OracleLattice:
 
     def set_outlet_density(self, rho: float) -> None:
         self._lib.orc_set_outlet_density(self._h, float(rho))
+
+    def set_inlet_offset(self, d: float) -> None:
+        """Offset added to the inlet density of eq. potential (controller tests)."""
+        self._lib.orc_set_inlet_offset(self._h, float(d))
+
+    def plain_inlet_density(self) -> float:
+        """The inlet density eq. potential gives for the next step."""
+        return float(self._lib.orc_plain_inlet_density(self._h))
 
     def init_equilibrium(self, rho=1.0, ux=0.0, uy=0.0, uz=0.0) -> None:
         self._lib.orc_init_equilibrium(self._h, float(rho), float(ux), float(uy), float(uz))

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfluxlbm.so")
-SOURCES = [os.path.join(HERE, "csrc", s) for s in ("engine.hip", "lattice.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", s) for s in ("engine.hip", "mlp.hip", "lattice.cpp")]
 ARCH = os.environ.get("FLBM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,359 @@
+"""Learned inlet controller: inputs, training on plain-method runs, and the
+steps-to-tolerance comparison with the plain update.
+
+The paper's update of eq. potential makes the inlet flux exact at every
+step, so what lags is the outlet flux: the pore space has to be charged to
+the steady pressure field before Q_out reaches Q* (Sec. 3 reads the same lag
+off the saturation rate of its drainage runs). The network predicts the
+steady inlet-outlet density difference from the sample's statistics and the
+outlet-flux history; the library's controller kernel turns the prediction
+into an offset of the next step's inlet density that the plain update bounds
+(decaying trust bound on |Q_in - Q*| / Q*) and finally replaces (release
+tolerance). Every network product runs in the library's BF16 matrix-core
+kernels; this module only prepares inputs and labels and drives the runs.
+
+Command line::
+
+    python -m paper_1806_10589_amd.controller train --out paper_1806_10589_amd/controller_weights.npz
+    python -m paper_1806_10589_amd.controller evaluate --weights ... --n 128 --seed 5001
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import fluxlbm, inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "controller_weights.npz")
+N_IN = 32
+RESERVOIR = 6
+
+# controller settings used for training runs and evaluation
+DEFAULTS = dict(gain=1.0, trust0=4.0, release_tol=1e-3)
+
+
+# ---------------------------------------------------------------- inputs
+
+def kozeny_carman(mask: np.ndarray, reservoir_layers: int):
+    """Porosity, specific surface (pore-solid faces per voxel) and the
+    Kozeny-Carman permeability phi^3 d^2 / (180 (1 - phi)^2) of the sample
+    (reservoirs excluded), with the grain size d = 6 (1 - phi) / S_v."""
+    m = np.asarray(mask, dtype=bool)
+    core = m[reservoir_layers:m.shape[0] - reservoir_layers] if reservoir_layers else m
+    phi = 1.0 - core.mean()
+    # faces between a pore and a solid voxel: periodic in x and y, not in z
+    faces = np.count_nonzero(core[1:] != core[:-1])
+    faces += np.count_nonzero(core != np.roll(core, 1, axis=1))
+    faces += np.count_nonzero(core != np.roll(core, 1, axis=2))
+    sv = faces / core.size
+    d = 6.0 * (1.0 - phi) / max(sv, 1e-12)
+    k = phi ** 3 * d * d / (180.0 * max(1.0 - phi, 1e-6) ** 2)
+    return float(phi), float(sv), float(k)
+
+
+def geometry_features(mask: np.ndarray, *, tau: float, q_target: float,
+                      reservoir_layers: int = RESERVOIR):
+    """The 15 static inputs and the reference density difference drho_ref
+    (Darcy's law with the Kozeny-Carman permeability:
+    drho = 3 nu q L / k, q = Q* / (nx ny), nu = (tau - 1/2) / 3)."""
+    m = np.asarray(mask, dtype=bool)
+    nz, ny, nx = m.shape
+    core = m[reservoir_layers:nz - reservoir_layers] if reservoir_layers else m
+    phi, sv, k = kozeny_carman(m, reservoir_layers)
+    slices = 1.0 - core.reshape(core.shape[0], -1).mean(axis=1)
+    q = q_target / (nx * ny)
+    nu = (tau - 0.5) / 3.0
+    length = core.shape[0]
+    drho_ref = 3.0 * nu * max(q, 1e-30) * length / max(k, 1e-12)
+    g = np.zeros(15, dtype=np.float64)
+    g[0] = 2.0 * phi - 0.6
+    g[1] = 2.0 * sv - 0.5
+    g[2:10] = 5.0 * (slices[:8] - phi) if len(slices) >= 8 else 0.0  # first slices from the inlet
+    g[10] = 10.0 * slices.std()
+    g[11] = math.log10(k) / 2.0 + 1.0
+    g[12] = math.log10(length) / 2.0 - 1.0
+    g[13] = 2.0 * (tau - 0.9)
+    g[14] = math.log10(max(q, 1e-30)) / 2.0 + 2.5
+    return g.astype(np.float32), float(drho_ref)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Glorot-uniform weights and zero biases (numpy PCG64)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_out, fan_in in ((128, N_IN), (128, 1), (128, 128), (128, 1), (1, 128), (1, 1)):
+        if fan_in == 1:
+            parts.append(np.zeros(fan_out))
+        else:
+            lim = math.sqrt(6.0 / (fan_in + fan_out))
+            parts.append(rng.uniform(-lim, lim, fan_out * fan_in))
+    return np.concatenate(parts).astype(np.float32)
+
+
+# ---------------------------------------------------------------- runs
+
+def two_step_error(qout: np.ndarray, q_target: float) -> np.ndarray:
+    """|Qbar - Q*| / Q* with Qbar the mean of two consecutive outlet fluxes
+    (BGK carries a period-two oscillation); entry i covers steps i, i+1."""
+    q = np.asarray(qout, np.float64)
+    return np.abs(0.5 * (q[1:] + q[:-1]) - q_target) / abs(q_target)
+
+
+def steps_to_tol(qout: np.ndarray, q_target: float, tol: float):
+    """Steps after which the two-step mean error stays within tol for the
+    rest of the record, or None if the last entry is outside."""
+    e = two_step_error(qout, q_target)
+    bad = np.nonzero(~(e <= tol))[0]
+    if len(bad) == 0:
+        return 2
+    if bad[-1] == len(e) - 1:
+        return None
+    return int(bad[-1] + 2)
+
+
+def make_sample(n: int, porosity: float, seed: int, *, tau: float, darcy: float,
+                precision: str = "fp32", watchdog_every: int = 4096):
+    mask, phi, _ = inputs.sphere_pack(n, porosity, seed, reservoir_layers=RESERVOIR)
+    q = darcy * mask.shape[1] * mask.shape[2]
+    kw = dict(tau=tau, q_target=q, precision=precision, reservoir_layers=RESERVOIR,
+              watchdog_every=watchdog_every)
+    return mask, kw
+
+
+def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_margin=2000,
+        max_steps=400000, chunk=4096, record=False, settle_tol=None, settings=None):
+    """Run from rest until the two-step mean outlet error has stayed within
+    ``settle_tol`` (default tol) for max(min_margin, margin_frac * t) steps.
+
+    With a network the controller is attached: active (trust0 from the
+    settings) or observing (trust0 = 0: the plain method exactly, inputs
+    recorded). Returns a dict with steps_to_tol, the history (rho_in, Q_in,
+    Q_out per step) and, with ``record``, the network inputs and the
+    controller's (drho, rho_plain, r, offset) per step.
+    """
+    s = dict(DEFAULTS, **(settings or {}))
+    settle_tol = tol if settle_tol is None else settle_tol
+    lat = fluxlbm.Lattice(mask, **kw)
+    try:
+        lat.init_equilibrium()
+        geom, drho_ref = geometry_features(mask, tau=kw["tau"], q_target=kw["q_target"],
+                                           reservoir_layers=kw.get("reservoir_layers", RESERVOIR))
+        nz = mask.shape[0]
+        if net is not None:
+            lat.set_controller(net, geom, drho_ref=drho_ref, gain=s["gain"],
+                               trust0=s["trust0"] if active else 0.0, release_tol=s["release_tol"],
+                               trust_steps=int(s.get("trust_steps", 4 * nz * nz)))
+        q = kw["q_target"]
+        hist, xs, auxs = [], [], []
+        t0 = time.perf_counter()
+        while lat.step_count < max_steps:
+            k = min(chunk, max_steps - lat.step_count)
+            lat.step(k)
+            h = lat.history(k)
+            hist.append(h[:, :3].copy())
+            if record and net is not None:
+                x, aux = lat.controller_trace(k)
+                xs.append(x)
+                auxs.append(aux)
+            qo = np.concatenate([hh[:, 2] for hh in hist])
+            st = steps_to_tol(qo, q, settle_tol)
+            if st is not None and lat.step_count - st >= max(min_margin, margin_frac * st):
+                break
+        secs = time.perf_counter() - t0
+        hist = np.concatenate(hist)
+        out = dict(steps=int(lat.step_count), secs=secs, hist=hist, drho_ref=drho_ref, geometry=geom,
+                   steps_to_tol=steps_to_tol(hist[:, 2], q, tol), q_target=q)
+        if net is not None:
+            out["controller"] = lat.controller_state()
+        if record and net is not None:
+            out["x"] = np.concatenate(xs)
+            out["aux"] = np.concatenate(auxs)
+        return out
+    finally:
+        lat.close()
+
+
+def steady_density(res, window=2048):
+    """Steady inlet density: mean over the last window steps (an even count
+    averages the period-two oscillation)."""
+    r = res["hist"][-window:, 0]
+    return float(r.mean())
+
+
+# ---------------------------------------------------------------- data
+
+def label(rho_inf: float, drho_ref: float, rho_out: float = 1.0) -> float:
+    """Target of the network: log(drho_inf / drho_ref), clipped to [-4, 4]."""
+    d = rho_inf - rho_out
+    if not d > 0.0:
+        return -4.0
+    return float(np.clip(math.log(d / drho_ref), -4.0, 4.0))
+
+
+def pick_rows(n_rows: int, k: int, seed: int) -> np.ndarray:
+    """About k rows: half log-spaced in time (the early transient), half uniform."""
+    rng = np.random.default_rng(seed)
+    a = np.unique(np.geomspace(1, n_rows, k // 2).astype(np.int64) - 1)
+    b = rng.integers(0, n_rows, k - len(a))
+    return np.unique(np.concatenate([a, b]))
+
+
+def training_family(count: int, seed0: int = 1000):
+    """Seeded training samples: sphere packs with edges in {48, 64, 80, 96,
+    128}, porosity in [0.22, 0.40], tau in [0.6, 1.2], Darcy velocity
+    log-uniform in [3e-6, 3e-5]."""
+    rng = np.random.default_rng(seed0)
+    out = []
+    for i in range(count):
+        out.append(dict(n=int(rng.choice([48, 64, 80, 96, 128])), porosity=float(rng.uniform(0.22, 0.40)),
+                        seed=seed0 + 1 + i, tau=float(rng.uniform(0.6, 1.2)),
+                        darcy=float(10 ** rng.uniform(math.log10(3e-6), math.log10(3e-5)))))
+    return out
+
+
+def train_network(net, X, T, *, steps, batch=1024, lr=2e-3, lr_end=1e-4, seed=0, log=None):
+    """Adam on the mean squared error, cosine learning-rate decay; X, T are
+    torch device tensors. The forward and backward products and the update
+    run in the library's kernels."""
+    import torch
+
+    g = torch.Generator(device=X.device)
+    g.manual_seed(seed)
+    n = X.shape[0]
+    b = min(batch, n, net.max_batch)
+    losses = []
+    for i in range(steps):
+        idx = torch.randint(0, n, (b,), device=X.device, generator=g)
+        a = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * i / max(1, steps - 1)))
+        want = (i % 200 == 0) or i == steps - 1
+        loss = net.train_step(X[idx], T[idx], a, want_loss=want)
+        if want:
+            losses.append((i, loss))
+            if log:
+                log(f"  train step {i}: loss {loss:.5f}")
+    return losses
+
+
+def train(out_path: str, *, samples: int = 40, dagger_rounds: int = 2, steps: int = 4000,
+          rows_per_run: int = 600, seed: int = 7, log=print, settings=None):
+    import torch
+
+    dev = torch.device("cuda:0")
+    fam = training_family(samples)
+    net = fluxlbm.Mlp(4096)
+    net.set_params(init_params(seed))
+    Xs, Ts, info = [], [], []
+    # plain runs (observing controller): steady density and the inputs of every step
+    cases = []
+    for i, c in enumerate(fam):
+        mask, kw = make_sample(c["n"], c["porosity"], c["seed"], tau=c["tau"], darcy=c["darcy"])
+        res = run(mask, kw, net=net, active=False, record=True, settle_tol=1e-4, max_steps=12 * c["n"] ** 2)
+        rho_inf = steady_density(res)
+        lab = label(rho_inf, res["drho_ref"])
+        rows = pick_rows(len(res["x"]), rows_per_run, seed + i)
+        Xs.append(res["x"][rows])
+        Ts.append(np.full(len(rows), lab, np.float32))
+        cases.append((mask, kw, lab, c))
+        info.append(dict(c, plain_steps_to_tol=res["steps_to_tol"], label=lab, steps=res["steps"]))
+        log(f"plain {i}: n={c['n']} phi={c['porosity']:.3f} tau={c['tau']:.2f} darcy={c['darcy']:.2e} "
+            f"steps_to_tol={res['steps_to_tol']} label={lab:.3f} ({res['secs']:.1f}s)")
+
+    def fit(tag):
+        X = torch.from_numpy(np.concatenate(Xs)).to(dev)
+        T = torch.from_numpy(np.concatenate(Ts)).to(dev)
+        log(f"{tag}: {X.shape[0]} rows")
+        return train_network(net, X, T, steps=steps, seed=seed, log=log)
+
+    losses = fit("fit 0")
+    # DAgger: inputs met under the network's own control, labelled with the
+    # same steady density
+    for rnd in range(dagger_rounds):
+        for i, (mask, kw, lab, c) in enumerate(cases):
+            res = run(mask, kw, net=net, active=True, record=True, max_steps=12 * c["n"] ** 2,
+                      settings=settings)
+            rows = pick_rows(len(res["x"]), rows_per_run, seed + 1000 * (rnd + 1) + i)
+            Xs.append(res["x"][rows])
+            Ts.append(np.full(len(rows), lab, np.float32))
+            info[i][f"learned_steps_to_tol_r{rnd}"] = res["steps_to_tol"]
+            log(f"dagger {rnd} run {i}: steps_to_tol learned={res['steps_to_tol']} "
+                f"plain={info[i]['plain_steps_to_tol']}")
+        losses = fit(f"fit {rnd + 1}")
+    params = net.get_params()
+    meta = dict(samples=samples, dagger_rounds=dagger_rounds, steps=steps, rows_per_run=rows_per_run,
+                seed=seed, settings=dict(DEFAULTS, **(settings or {})), final_loss=losses[-1][1],
+                family=info)
+    np.savez(out_path, params=params, meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+    net.close()
+    return meta
+
+
+def load_weights(path: str = DEFAULT_WEIGHTS):
+    z = np.load(path, allow_pickle=False)
+    return z["params"].astype(np.float32), json.loads(bytes(z["meta"]).decode())
+
+
+def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000):
+    """Steps to tol for the plain update and for the learned controller on
+    the same sample and GPU."""
+    net = fluxlbm.Mlp(16)
+    net.set_params(params)
+    try:
+        plain = run(mask, kw, tol=tol, max_steps=max_steps)
+        learned = run(mask, kw, net=net, active=True, tol=tol, max_steps=max_steps, settings=settings)
+    finally:
+        pass
+    out = dict(plain_steps=plain["steps_to_tol"], learned_steps=learned["steps_to_tol"],
+               plain_secs=plain["secs"], learned_secs=learned["secs"],
+               controller=learned.get("controller"))
+    if plain["steps_to_tol"] and learned["steps_to_tol"]:
+        out["gain"] = plain["steps_to_tol"] / learned["steps_to_tol"]
+    net.close()
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", default=DEFAULT_WEIGHTS)
+    t.add_argument("--samples", type=int, default=40)
+    t.add_argument("--dagger", type=int, default=2)
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--seed", type=int, default=7)
+    e = sub.add_parser("evaluate")
+    e.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    e.add_argument("--n", type=int, nargs="+", default=[128])
+    e.add_argument("--porosity", type=float, default=0.25)
+    e.add_argument("--seed", type=int, nargs="+", default=[5001])
+    e.add_argument("--tau", type=float, default=0.8)
+    e.add_argument("--darcy", type=float, default=1e-5)
+    e.add_argument("--trust0", type=float, default=None)
+    e.add_argument("--release-tol", type=float, default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "train":
+        meta = train(a.out, samples=a.samples, dagger_rounds=a.dagger, steps=a.steps, seed=a.seed,
+                     log=lambda m: print(m, flush=True))
+        print(json.dumps({"final_loss": meta["final_loss"]}))
+    else:
+        params, meta = load_weights(a.weights)
+        settings = {}
+        if a.trust0 is not None:
+            settings["trust0"] = a.trust0
+        if a.release_tol is not None:
+            settings["release_tol"] = a.release_tol
+        for n in a.n:
+            for sd in a.seed:
+                mask, kw = make_sample(n, a.porosity, sd, tau=a.tau, darcy=a.darcy)
+                r = evaluate(params, mask, kw, settings=settings)
+                print(json.dumps(dict(n=n, seed=sd, porosity=a.porosity, tau=a.tau, darcy=a.darcy, **r)),
+                      flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
         const DevState *st = p.st;
         if (s < p.a_in) {
             // pure non-wetting injection: A_5 = w_5 (1 + 9/2 u_z), B_5 = 0
-            const double drho_in = (p.rho0 * st->q_target + st->s_carry[p.rd]) / (double)(p.a_in);
+            const double drho_in = inlet_drho(st, p.rd, p.rho0, p.a_in);
             const double uz = inlet_velocity(g, drho_in, p.rho0);
             a[5] = (R)(d3q19::weight7(5) * (1.0 + 4.5 * uz));
             b[5] = (R)0;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
 
     double uz_in = 0.0, uz_out = 0.0;
     if (tile < a.nt_in && s < a.a_in) {
-        const double drho_in = (a.rho0 * a.st->q_target + a.st->s_carry[a.rd]) / (double)a.a_in;
+        const double drho_in = inlet_drho(a.st, a.rd, a.rho0, a.a_in);
         uz_in = inlet_condition(g, drho_in, a.rho0);
     }
     if (tile >= a.tout0 && s >= a.out0 && s < a.n) uz_out = outlet_condition(g, a.st->drho_out, a.rho0);

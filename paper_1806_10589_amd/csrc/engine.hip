@@ -25,6 +25,8 @@
 #include "colour.h"
 #include "kernels.h"
 #include "lattice.h"
+#include "mlp.h"
+#include "mlp_ctx.h"
 
 using namespace flbm;
 
@@ -74,6 +76,12 @@ struct flbm_ctx {
     void *ca[2] = {nullptr, nullptr}, *cb[2] = {nullptr, nullptr};  // [7][n_pad] each
     void *na = nullptr, *nb = nullptr, *phi = nullptr;              // [n_pad] each
     double *obs_na = nullptr, *obs_nb = nullptr;
+    // learned inlet controller
+    bool ctrl_on = false;
+    const flbm_mlp *ctrl_net = nullptr;
+    flbm_controller_params ctrl{};
+    float *ctrl_feat = nullptr;   // [16] geometry inputs on the device
+    float *ctrl_trace = nullptr;  // [HIST_CAP][CTRL_REC] decision records
 
     // host bookkeeping
     int64_t steps = 0;
@@ -150,6 +158,8 @@ size_t carve(flbm_ctx *c, char *base)
     char *ob = take((size_t)c->obs_slots * sizeof(uint32_t));
     char *hi = take((size_t)HIST_CAP * HIST_STRIDE * sizeof(double));
     char *fl = take((size_t)4 * npad * sizeof(double));
+    char *cf = take(16 * sizeof(float));
+    char *ct = take((size_t)HIST_CAP * 40 * sizeof(float));
     char *cc[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     char *on = nullptr, *ob2 = nullptr;
     if (c->colour) {
@@ -173,6 +183,8 @@ size_t carve(flbm_ctx *c, char *base)
         c->obs_bad = (uint32_t *)ob;
         c->hist = (double *)hi;
         c->fields = (double *)fl;
+        c->ctrl_feat = (float *)cf;
+        c->ctrl_trace = (float *)ct;
         if (c->colour) {
             c->ca[0] = cc[0];
             c->ca[1] = cc[1];
@@ -327,7 +339,7 @@ void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
     if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
 }
 
-void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
+void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
 {
     if (c->colour) {
         if (is_fp64(c))
@@ -338,6 +350,115 @@ void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
         return;
     }
     with_storage(c, [&](auto tag) { launch_step<decltype(tag)>(c, s, from, obs); });
+}
+
+// Learned inlet controller (one workgroup, after each step kernel). From the
+// step history it builds the network's inputs -- 15 geometry values, 16
+// outlet-flux errors at log-spaced lags and the scale of the current
+// inlet-outlet density difference -- and runs the network (MFMA, BF16
+// operands, FP32 accumulation). The output is the predicted steady
+// inlet-outlet density difference, as the log of its ratio to a reference;
+// the step from the plain density of the next step towards that proposal is
+// clipped so that the inlet flux stays within the decaying trust bound, and
+// dropped once the outlet flux has met the release tolerance, for Q* <= 0, or
+// when it is not finite.
+constexpr int CTRL_LAGS[16] = {1, 2, 3, 6, 11, 20, 36, 65, 119, 215, 391, 710, 1290, 2345, 4260, 7740};
+constexpr int CTRL_REC = 40;  // floats per trace record: x[32], then 4 doubles
+
+struct CtrlArgs {
+    DevState *st;
+    const double *hist;
+    float *trace;  // [HIST_CAP][CTRL_REC]
+    int32_t hist_cap;
+    int32_t trust_steps;
+    int32_t rd_next;
+    int32_t pad_;
+    const float *params;
+    const float *geometry;
+    double rho0, a_in, drho_ref, gain, trust0, release_tol;
+};
+
+__global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
+{
+    __shared__ float x[mlp::N_IN];
+    __shared__ float h1[mlp::N_HID], h2[mlp::N_HID];
+    DevState *st = c.st;
+    const int64_t t = st->step;  // steps completed; the last one has index t - 1
+    const double qs = st->q_target;
+    const double qn = qs != 0.0 ? fabs(qs) : 1.0;
+    auto qout = [&](int64_t k) -> double {  // outlet flux of step k; rest before the first step
+        if (k < 0) return 0.0;
+        const double v = c.hist[(k % c.hist_cap) * HIST_STRIDE + 2];
+        return isfinite(v) ? v : 0.0;
+    };
+    const double rin = t >= 1 ? c.hist[((t - 1) % c.hist_cap) * HIST_STRIDE + 0] : 1.0 + st->drho_out;
+    const double drho = rin - 1.0 - st->drho_out;
+    if (threadIdx.x < mlp::N_IN) {
+        const int i = threadIdx.x;
+        float v;
+        if (i < 15) {
+            v = c.geometry[i];
+        } else if (i < 31) {
+            const int lag = CTRL_LAGS[i - 15];
+            const double e = (0.5 * (qout(t - lag) + qout(t - lag - 1)) - qs) / qn;
+            v = (float)fmin(2.0, fmax(-2.0, e));
+        } else {
+            const double lg = drho > 0.0 ? log10(drho / c.drho_ref) / 3.0 : -1.0;
+            v = isfinite(lg) ? (float)fmin(1.0, fmax(-1.0, lg)) : -1.0f;
+        }
+        x[i] = v;
+    }
+    __syncthreads();
+    const float y = mlp::forward_one(c.params, x, h1, h2);
+    float *rec = c.trace + (size_t)((t - 1 + c.hist_cap) % c.hist_cap) * CTRL_REC;
+    if (threadIdx.x < mlp::N_IN) rec[threadIdx.x] = x[threadIdx.x];
+    if (threadIdx.x == 0) {
+        const double e2 = fabs(0.5 * (qout(t - 1) + qout(t - 2)) - qs) / qn;
+        if (t >= 2 && e2 <= c.release_tol) st->ctrl_released = 1u;
+        const int64_t n = st->ctrl_steps;
+        const double bound =
+            c.trust_steps > 0 ? c.trust0 * fmax(0.0, 1.0 - (double)n / (double)c.trust_steps) : 0.0;
+        const double limit = bound * c.rho0 * qn / c.a_in;
+        const double rho_plain = 1.0 + inlet_drho_plain(st, c.rd_next, c.rho0, (int64_t)c.a_in);
+        const double r = fmin(4.0, fmax(-4.0, (double)y));
+        const double rho_hat = 1.0 + st->drho_out + c.drho_ref * exp(r);
+        double delta = c.gain * (rho_hat - rho_plain);
+        if (!isfinite(delta) || !(qs > 0.0) || st->ctrl_released) delta = 0.0;
+        delta = fmin(limit, fmax(-limit, delta));
+        st->ctrl_delta = delta;
+        st->ctrl_steps = n + 1;
+        double *aux = (double *)(rec + 32);
+        aux[0] = drho;
+        aux[1] = rho_plain;
+        aux[2] = (double)y;
+        aux[3] = delta;
+    }
+}
+
+void launch_controller(flbm_ctx *c, hipStream_t s, int rd_next)
+{
+    CtrlArgs a{};
+    a.st = c->st;
+    a.hist = c->hist;
+    a.trace = c->ctrl_trace;
+    a.hist_cap = HIST_CAP;
+    a.trust_steps = c->ctrl.trust_steps;
+    a.rd_next = rd_next;
+    a.params = c->ctrl_net->params;
+    a.geometry = c->ctrl_feat;
+    a.rho0 = c->p.rho0;
+    a.a_in = (double)c->lat.a_in;
+    a.drho_ref = c->ctrl.drho_ref;
+    a.gain = c->ctrl.gain;
+    a.trust0 = c->ctrl.trust0;
+    a.release_tol = c->ctrl.release_tol;
+    hipLaunchKernelGGL(k_controller, dim3(1), dim3(256), 0, s, a);
+}
+
+void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
+{
+    launch_step_plain(c, s, from, obs);
+    if (c->ctrl_on) launch_controller(c, s, from ^ 1);
 }
 
 void drop_graphs(flbm_ctx *c)
@@ -604,6 +725,75 @@ flbm_status flbm_get_site_coords(const flbm_ctx *c, int32_t *xyz)
 {
     if (!c || !xyz) return FLBM_EINVAL;
     std::memcpy(xyz, c->lat.coords.data(), c->lat.coords.size() * sizeof(int32_t));
+    return FLBM_OK;
+}
+
+flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_controller_params *p)
+{
+    if (!c) return FLBM_EINVAL;
+    if (net && !p) return FLBM_EINVAL;
+    if (c->p.z_mode != FLBM_Z_FLUX && net) return fail(c, FLBM_ESTATE, "the controller needs the flux inlet");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    if (net) {
+        if (!(p->trust0 >= 0.0) || !std::isfinite(p->gain) || p->trust_steps < 0 || !(p->release_tol >= 0.0) ||
+            !(p->drho_ref > 0.0) || !std::isfinite(p->drho_ref))
+            return fail(c, FLBM_EINVAL, "bad controller parameters");
+        c->ctrl = *p;
+        c->ctrl_net = net;
+        float g[16] = {0};
+        std::memcpy(g, p->geometry, sizeof(p->geometry));
+        HIPCHK(c, hipMemcpy(c->ctrl_feat, g, sizeof(g), hipMemcpyHostToDevice));
+    }
+    c->ctrl_on = net != nullptr;
+    // fresh controller state: no offset, not released, no decisions taken
+    const double zero = 0.0;
+    const int64_t z64 = 0;
+    const uint32_t z32 = 0;
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_delta, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_steps, &z64, sizeof(z64), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_released, &z32, sizeof(z32), hipMemcpyHostToDevice));
+    return FLBM_OK;
+}
+
+flbm_status flbm_controller_state(flbm_ctx *c, int32_t *active, int32_t *released, double *delta, int64_t *decisions)
+{
+    if (!c) return FLBM_EINVAL;
+    if (active) *active = c->ctrl_on ? 1 : 0;
+    if (!c->ready) {
+        if (released) *released = 0;
+        if (delta) *delta = 0.0;
+        if (decisions) *decisions = 0;
+        return FLBM_OK;
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    DevState d{};
+    HIPCHK(c, hipMemcpy(&d, c->st, sizeof(d), hipMemcpyDeviceToHost));
+    if (released) *released = (int32_t)d.ctrl_released;
+    if (delta) *delta = d.ctrl_delta;
+    if (decisions) *decisions = d.ctrl_steps;
+    return FLBM_OK;
+}
+
+flbm_status flbm_controller_trace(flbm_ctx *c, int32_t n, float *x, double *aux)
+{
+    if (!c || n < 0 || (n > 0 && (!x || !aux))) return FLBM_EINVAL;
+    if (n == 0) return FLBM_OK;
+    if (!c->ready || n > HIST_CAP) return fail(c, FLBM_EBOUND, "more records than the ring holds");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    DevState d{};
+    HIPCHK(c, hipMemcpy(&d, c->st, sizeof(d), hipMemcpyDeviceToHost));
+    if (n > d.ctrl_steps) return fail(c, FLBM_EBOUND, "fewer decisions taken than requested");
+    std::vector<float> rec((size_t)HIST_CAP * CTRL_REC);
+    HIPCHK(c, hipMemcpy(rec.data(), c->ctrl_trace, rec.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t k = d.step - n + i;  // decision taken after step k
+        const float *r = rec.data() + (size_t)(k % HIST_CAP) * CTRL_REC;
+        std::memcpy(x + (size_t)i * 32, r, 32 * sizeof(float));
+        std::memcpy(aux + (size_t)i * 4, r + 32, 4 * sizeof(double));
+    }
     return FLBM_OK;
 }
 

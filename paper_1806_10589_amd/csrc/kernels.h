@@ -50,6 +50,7 @@ struct DevState {
     double s_carry[2];    // inlet consistency sum (deviation form) for the next step,
                           // slot = index of the buffer that step reads
     double omega;         // 1/tau (0 turns collision off)
+    double ctrl_delta;    // controller's inlet density offset for the next step (0: plain update)
     double obs_mass;      // on-demand observables
     double obs_umax;
     int64_t step;         // steps completed
@@ -57,7 +58,25 @@ struct DevState {
     uint32_t b_ticket;
     uint32_t unstable;    // sticky watchdog flag
     uint32_t obs_bad;
+    int64_t ctrl_steps;   // controller decisions taken
+    uint32_t ctrl_released;  // sticky: the outlet flux met the tolerance, plain update from now on
+    uint32_t pad_;
 };
+
+// Inlet density minus one for the step reading s_carry[rd] (eq. potential):
+// (rho0 Q* + sum_i Kt_i) / A, plus the controller's offset when one is active.
+// Inlet density minus one for the step that reads parity rd: the update of
+// eq. potential, rho_in = (rho0 Q* + sum_i K_i) / A in deviation form, plus
+// the learned controller's offset (zero unless a controller is attached).
+__device__ __forceinline__ double inlet_drho_plain(const DevState *st, int rd, double rho0, int64_t a_in)
+{
+    return (rho0 * st->q_target + st->s_carry[rd]) / (double)a_in;
+}
+
+__device__ __forceinline__ double inlet_drho(const DevState *st, int rd, double rho0, int64_t a_in)
+{
+    return inlet_drho_plain(st, rd, rho0, a_in) + st->ctrl_delta;
+}
 
 struct StepArgs {
     int64_t n, npad;
@@ -533,7 +552,7 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
         const int64_t t = st->step;
         double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
         if (a.flux_mode) {
-            h[0] = 1.0 + (a.rho0 * st->q_target + st->s_carry[a.rd]) / (double)a.a_in;
+            h[0] = 1.0 + inlet_drho(st, a.rd, a.rho0, a.a_in);
             h[1] = ti;
             h[2] = to;
             st->s_carry[a.rd ^ 1] = tn;
@@ -609,8 +628,7 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
 
     double uz_in = 0.0, uz_out = 0.0;
     if (tile < a.nt_in) {
-        // eq. potential: rho_in - 1 = (rho0 Q* + sum_i Kt_i) / A
-        const double drho_in = (a.rho0 * a.st->q_target + a.st->s_carry[a.rd]) / (double)a.a_in;
+        const double drho_in = inlet_drho(a.st, a.rd, a.rho0, a.a_in);
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (s0 + v < a.a_in) uz_in += inlet_condition(g[v], drho_in, a.rho0);

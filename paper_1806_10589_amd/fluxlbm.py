@@ -42,6 +42,14 @@ class FlbmError(RuntimeError):
         super().__init__(msg)
 
 
+class flbm_controller_params(ctypes.Structure):
+    _fields_ = [
+        ("geometry", ctypes.c_float * 15), ("reserved", ctypes.c_float),
+        ("drho_ref", ctypes.c_double), ("gain", ctypes.c_double), ("trust0", ctypes.c_double), ("release_tol", ctypes.c_double),
+        ("trust_steps", ctypes.c_int32), ("reserved2", ctypes.c_int32),
+    ]
+
+
 class flbm_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
@@ -96,6 +104,19 @@ _SIGS = {
     "flbm_device_layout": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I64P],
     "flbm_profile_kernels": [_P, _I32, _DP, _DP],
     "flbm_copy_kernel": [_P, _P, ctypes.c_size_t, _P],
+    "flbm_mlp_create": [_I32, _P, ctypes.POINTER(_P)],
+    "flbm_mlp_destroy": [_P],
+    "flbm_mlp_num_params": [ctypes.POINTER(_I32)],
+    "flbm_mlp_set_params": [_P, _P, _I32],
+    "flbm_mlp_get_params": [_P, _P, _I32],
+    "flbm_mlp_forward": [_P, _P, _P, _I32],
+    "flbm_mlp_gradients": [_P, _P, _P, _I32, _P, _P],
+    "flbm_mlp_train_step": [_P, _P, _P, _I32, ctypes.c_float, _P],
+    "flbm_gemm_bf16": [_P, ctypes.c_int64, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_int64, _P,
+                       ctypes.c_int64, _I32, _I32, _I32, _P],
+    "flbm_set_controller": [_P, _P, _P],
+    "flbm_controller_state": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _DP, _I64P],
+    "flbm_controller_trace": [_P, _I32, _P, _P],
     "flbm_status_string": [_I32],
     "flbm_last_error": [_P],
 }
@@ -325,7 +346,135 @@ def flbm_copy_kernel(src: int, dst: int, nbytes: int, stream: int | None = None)
     _check(load_library().flbm_copy_kernel(src, dst, nbytes, stream or None), "flbm_copy_kernel")
 
 
+def flbm_mlp_create(max_batch: int, stream: int | None = None):
+    out = _P()
+    _check(load_library().flbm_mlp_create(int(max_batch), stream or None, ctypes.byref(out)), "flbm_mlp_create")
+    return out.value
+
+
+def flbm_mlp_destroy(m) -> None:
+    _check(load_library().flbm_mlp_destroy(m), "flbm_mlp_destroy")
+
+
+def flbm_mlp_num_params() -> int:
+    n = _I32()
+    _check(load_library().flbm_mlp_num_params(ctypes.byref(n)), "flbm_mlp_num_params")
+    return int(n.value)
+
+
+def flbm_mlp_set_params(m, params: np.ndarray) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load_library().flbm_mlp_set_params(m, p.ctypes.data, p.size), "flbm_mlp_set_params")
+
+
+def flbm_mlp_get_params(m) -> np.ndarray:
+    p = np.empty(flbm_mlp_num_params(), dtype=np.float32)
+    _check(load_library().flbm_mlp_get_params(m, p.ctypes.data, p.size), "flbm_mlp_get_params")
+    return p
+
+
+def flbm_mlp_forward(m, dev_x: int, dev_y: int, batch: int) -> None:
+    _check(load_library().flbm_mlp_forward(m, dev_x, dev_y, int(batch)), "flbm_mlp_forward")
+
+
+def flbm_mlp_gradients(m, dev_x: int, dev_t: int, batch: int):
+    g = np.empty(flbm_mlp_num_params(), dtype=np.float32)
+    loss = np.empty(1, dtype=np.float32)
+    _check(load_library().flbm_mlp_gradients(m, dev_x, dev_t, int(batch), g.ctypes.data, loss.ctypes.data),
+           "flbm_mlp_gradients")
+    return g, float(loss[0])
+
+
+def flbm_mlp_train_step(m, dev_x: int, dev_t: int, batch: int, lr: float, want_loss: bool = False):
+    loss = np.empty(1, dtype=np.float32)
+    _check(load_library().flbm_mlp_train_step(m, dev_x, dev_t, int(batch), float(lr),
+                                              loss.ctypes.data if want_loss else None), "flbm_mlp_train_step")
+    return float(loss[0]) if want_loss else None
+
+
+def flbm_gemm_bf16(a: int, a_rs: int, a_cs: int, b: int, b_rs: int, b_cs: int, c: int, c_rs: int,
+                   m: int, n: int, k: int, stream: int | None = None) -> None:
+    _check(load_library().flbm_gemm_bf16(a, a_rs, a_cs, b, b_rs, b_cs, c, c_rs, m, n, k, stream or None),
+           "flbm_gemm_bf16")
+
+
+def flbm_set_controller(ctx, net, params: flbm_controller_params | None) -> None:
+    _check(load_library().flbm_set_controller(ctx, net, ctypes.byref(params) if params is not None else None),
+           "flbm_set_controller", ctx)
+
+
+def flbm_controller_state(ctx):
+    a, r, d, n = _I32(), _I32(), _D(), ctypes.c_int64()
+    _check(load_library().flbm_controller_state(ctx, ctypes.byref(a), ctypes.byref(r), ctypes.byref(d),
+                                                ctypes.byref(n)), "flbm_controller_state", ctx)
+    return bool(a.value), bool(r.value), float(d.value), int(n.value)
+
+
+def flbm_controller_trace(ctx, n: int):
+    x = np.empty((int(n), 32), dtype=np.float32)
+    aux = np.empty((int(n), 4), dtype=np.float64)
+    _check(load_library().flbm_controller_trace(ctx, int(n), x.ctypes.data, aux.ctypes.data),
+           "flbm_controller_trace", ctx)
+    return x, aux
+
+
 # ------------------------------------------------------------------ convenience
+
+class Mlp:
+    """The controller network on ``device``, working on torch's current
+    stream; inputs and targets are torch FP32 device tensors."""
+
+    def __init__(self, max_batch: int, device: str = "cuda:0"):
+        import torch
+
+        self.device = torch.device(device)
+        self._torch = torch
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.handle = flbm_mlp_create(max_batch, self.stream.cuda_stream)
+        self.max_batch = int(max_batch)
+        self.n_params = flbm_mlp_num_params()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            flbm_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, t, shape):
+        t = t.to(self.device, self._torch.float32).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return t
+
+    def set_params(self, p: np.ndarray):
+        flbm_mlp_set_params(self.handle, p)
+
+    def get_params(self) -> np.ndarray:
+        return flbm_mlp_get_params(self.handle)
+
+    def forward(self, x):
+        b = int(x.shape[0])
+        x = self._dev(x, (b, 32))
+        y = self._torch.empty(b, dtype=self._torch.float32, device=self.device)
+        flbm_mlp_forward(self.handle, x.data_ptr(), y.data_ptr(), b)
+        return y
+
+    def gradients(self, x, t):
+        b = int(x.shape[0])
+        x, t = self._dev(x, (b, 32)), self._dev(t, (b,))
+        return flbm_mlp_gradients(self.handle, x.data_ptr(), t.data_ptr(), b)
+
+    def train_step(self, x, t, lr, want_loss=False):
+        b = int(x.shape[0])
+        x, t = self._dev(x, (b, 32)), self._dev(t, (b,))
+        return flbm_mlp_train_step(self.handle, x.data_ptr(), t.data_ptr(), b, lr, want_loss)
+
 
 class Lattice:
     """A context whose device memory is one torch ``uint8`` tensor and whose
@@ -469,3 +618,26 @@ class Lattice:
 
     def layout(self):
         return flbm_device_layout(self.ctx)
+
+    def set_controller(self, net: "Mlp | None", geometry=None, *, drho_ref=1e-3, gain=1.0, trust0=0.5,
+                       release_tol=1e-3, trust_steps=20000):
+        if net is None:
+            flbm_set_controller(self.ctx, None, None)
+            self._ctrl_net = None
+            return
+        p = flbm_controller_params()
+        g = np.zeros(15, dtype=np.float32) if geometry is None else np.asarray(geometry, np.float32)
+        if g.shape != (15,):
+            raise ValueError("geometry must hold 15 features")
+        for i in range(15):
+            p.geometry[i] = float(g[i])
+        p.drho_ref = float(drho_ref)
+        p.gain, p.trust0, p.release_tol, p.trust_steps = float(gain), float(trust0), float(release_tol), int(trust_steps)
+        flbm_set_controller(self.ctx, net.handle, p)
+        self._ctrl_net = net  # the network must outlive the attachment
+
+    def controller_state(self):
+        return flbm_controller_state(self.ctx)
+
+    def controller_trace(self, n):
+        return flbm_controller_trace(self.ctx, n)

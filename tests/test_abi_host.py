@@ -38,6 +38,35 @@ def test_params_struct_layout():
     assert p.precision == fluxlbm.FLBM_FP32 and p.z_mode == fluxlbm.FLBM_Z_FLUX
 
 
+def test_struct_layouts_match_the_header(tmp_path):
+    # compile the header with the host C compiler and compare every field
+    # offset and the struct sizes with the ctypes mirrors
+    structs = {"flbm_params": fluxlbm.flbm_params,
+               "flbm_controller_params": fluxlbm.flbm_controller_params}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fluxlbm.h"', "int main(void){"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(out[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
+
+
+def test_mlp_parameter_count():
+    # 32 -> 128 -> 128 -> 1 with biases
+    assert fluxlbm.flbm_mlp_num_params() == 128 * 32 + 128 + 128 * 128 + 128 + 128 + 1
+
+
 def _params(mask, **kw):
     p = fluxlbm.flbm_default_params()
     p.nz, p.ny, p.nx = mask.shape

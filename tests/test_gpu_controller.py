@@ -1,0 +1,165 @@
+"""The learned inlet controller on the GPU: its decision rule against the FP64
+oracle controller on the dense oracle lattice, and the cases where the plain
+update of eq. potential must rule (trust0 = 0, a non-finite network, the
+decaying trust bound, release), plus the trained network's gain.
+
+Tolerances: the network's output differs from the oracle's (FP64 products
+of the same BF16 operands) by FP32 accumulation, below 2e-4 of its scale;
+an offset that is not clipped carries that difference times drho_ref exp(r);
+a clipped offset is the same FP64 number on both sides."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as mo
+from oracle.controller_oracle import OracleController
+from paper_1806_10589_amd import controller, fluxlbm, inputs
+from .gpu_helpers import pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _mask():
+    m, _, _ = inputs.sphere_pack((20, 12, 12), 0.6, 3, rmin=2, rmax=3, reservoir_layers=2)
+    return m
+
+
+def _params(seed, b3, scale=0.3):
+    p = scale * inputs.uniform_noise((mo.N_PARAMS,), seed)
+    p[-1] = b3
+    return p.astype(np.float32)
+
+
+GEOM = np.linspace(-0.5, 0.5, 15).astype(np.float32)
+
+
+@pytest.mark.parametrize("gain,trust0,b3", [(0.5, 2.0, 0.5), (0.2, 50.0, -0.3)])
+def test_decisions_match_oracle(gain, trust0, b3):
+    mask = _mask()
+    q = 0.02
+    lat, orc = pair(mask, precision="fp64", tau=0.9, q_target=q)
+    lat.init_equilibrium()
+    orc.init_equilibrium()
+    params = _params(81, b3)
+    net = fluxlbm.Mlp(16)
+    net.set_params(params)
+    kw = dict(drho_ref=1e-3, gain=gain, trust0=trust0, release_tol=1e-12, trust_steps=50)
+    lat.set_controller(net, GEOM, **kw)
+    oc = OracleController(params.astype(np.float64), GEOM, **kw)
+    n = 80
+    lat.step(n)
+    hg = lat.history(n)
+    ho = oc.run(orc, n, q_target=q)
+    x, aux = lat.controller_trace(n)
+    xo = np.array([r[0] for r in oc.records])
+    auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
+    assert np.max(np.abs(x - xo)) <= 1e-6
+    assert np.max(np.abs(aux[:, 1] - auxo[:, 1])) <= 1e-12          # rho_plain
+    assert np.max(np.abs(aux[:, 2] - auxo[:, 2])) <= 2e-4 * max(1.0, np.abs(auxo[:, 2]).max())
+    scale = kw["drho_ref"] * math.exp(4.0) * gain
+    assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 2e-4 * scale + 1e-15   # offsets
+    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 2e-4 * scale + 1e-12      # rho_in
+    assert np.max(np.abs(hg[:, 1] - ho[:, 1])) <= 1e-9 * q + 2e-4 * scale * orc.a_in
+    # the offsets did something, and the last 30 steps are plain (bound decayed)
+    assert np.max(np.abs(auxo[:50, 3])) > 1e-6
+    assert np.all(auxo[50:, 3] == 0.0) and np.all(aux[50:, 3] == 0.0)
+    assert np.allclose(hg[51:, 1], q, rtol=1e-10)
+    active, released, _, decisions = lat.controller_state()
+    assert active and not released and decisions == n
+    lat.close()
+    net.close()
+
+
+def _plain_and_controlled(params, ctrl, steps=300, precision="fp64"):
+    mask = _mask()
+    q = 0.02
+    a = fluxlbm.Lattice(mask, precision=precision, tau=0.9, q_target=q)
+    b = fluxlbm.Lattice(mask, precision=precision, tau=0.9, q_target=q)
+    a.init_equilibrium()
+    b.init_equilibrium()
+    net = fluxlbm.Mlp(16)
+    net.set_params(params)
+    b.set_controller(net, GEOM, **ctrl)
+    a.step(steps)
+    b.step(steps)
+    out = a.read_distributions(), b.read_distributions(), a.history(steps), b.history(steps), b
+    a.close()
+    return out, net
+
+
+def test_zero_trust_is_the_plain_method_bitwise():
+    (fa, fb, ha, hb, b), net = _plain_and_controlled(
+        _params(91, 2.0), dict(drho_ref=1e-3, trust0=0.0, release_tol=0.0, trust_steps=1000))
+    assert np.array_equal(fa, fb)
+    assert np.array_equal(ha[:, :3], hb[:, :3])
+    x, aux = b.controller_trace(300)
+    assert np.all(aux[:, 3] == 0.0) and np.all(np.isfinite(x))
+    b.close()
+    net.close()
+
+
+def test_non_finite_network_falls_back_to_plain():
+    p = _params(92, 0.0)
+    p[-1] = np.nan
+    (fa, fb, ha, hb, b), net = _plain_and_controlled(
+        p, dict(drho_ref=1e-3, trust0=5.0, release_tol=0.0, trust_steps=1000))
+    assert np.array_equal(fa, fb)
+    _, aux = b.controller_trace(300)
+    assert np.all(np.isnan(aux[:, 2])) and np.all(aux[:, 3] == 0.0)
+    b.close()
+    net.close()
+
+
+def test_trust_bound_clips_and_decays():
+    # r = 4 proposes a density far above anything reasonable: every offset is
+    # clipped to the bound, which decays to zero after trust_steps decisions
+    q, trust0, ts = 0.02, 0.2, 100
+    (fa, fb, ha, hb, b), net = _plain_and_controlled(
+        _params(93, 50.0), dict(drho_ref=1e-3, trust0=trust0, release_tol=0.0, trust_steps=ts), steps=200)
+    dev = np.abs(hb[:, 1] - q) / q        # |Q_in - Q*| / Q* per step
+    n = np.arange(200)
+    bound = trust0 * np.maximum(0.0, 1.0 - (n - 1) / ts)  # step k uses decision k-1
+    assert dev[0] <= 1e-9                  # the first step is plain
+    assert np.all(dev[1:] <= bound[1:] + 1e-9)
+    assert np.allclose(dev[1:ts], bound[1:ts], rtol=1e-6)  # clipped at the bound
+    assert np.all(dev[ts + 1:] <= 1e-9)    # then the plain method
+    b.close()
+    net.close()
+
+
+def test_release_returns_control_for_good():
+    (fa, fb, ha, hb, b), net = _plain_and_controlled(
+        _params(94, 50.0), dict(drho_ref=1e-3, trust0=1.0, release_tol=10.0, trust_steps=10 ** 6), steps=50)
+    _, released, delta, decisions = b.controller_state()
+    assert released and delta == 0.0 and decisions == 50
+    _, aux = b.controller_trace(50)
+    assert aux[0, 3] != 0.0 and np.all(aux[1:, 3] == 0.0)  # released from t >= 2
+    b.set_controller(None)
+    assert not b.controller_state()[0]
+    b.step(10)
+    assert np.allclose(b.history(10)[:, 1], 0.02, rtol=1e-9)
+    b.close()
+    net.close()
+
+
+def test_controller_rejected_without_flux_inlet():
+    mask = _mask()
+    lat = fluxlbm.Lattice(mask, precision="fp32", z_mode=fluxlbm.FLBM_Z_PERIODIC)
+    net = fluxlbm.Mlp(16)
+    with pytest.raises(fluxlbm.FlbmError) as e:
+        lat.set_controller(net, GEOM)
+    assert e.value.status == fluxlbm.FLBM_ESTATE
+    lat.close()
+    net.close()
+
+
+@pytest.mark.skipif(not os.path.exists(controller.DEFAULT_WEIGHTS), reason="no trained controller weights")
+def test_trained_controller_reaches_tolerance_sooner():
+    # a held-out sample of the training family's kind (seed outside it)
+    params, _ = controller.load_weights()
+    mask, kw = controller.make_sample(64, 0.3, 4242, tau=0.8, darcy=1e-5)
+    r = controller.evaluate(params, mask, kw, max_steps=200000)
+    assert r["plain_steps"] is not None and r["learned_steps"] is not None
+    assert r["learned_steps"] < r["plain_steps"], r
