@@ -32,7 +32,11 @@ CONFIGS = {
     "pack256h": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp16dev"),
     "pack512": dict(n=512, porosity=0.25, seed=5, reservoir=6, tau=0.8, darcy=1e-5, precision="fp32"),
     "slit": dict(slit=True, tau=1.0, q=0.5, precision="fp64"),
+    # 64 samples of uneven size in one batched launch per step
+    "batch64": dict(batch=64, seed=3, edge=(64, 192), porosity=(0.2, 0.45), darcy=(1e-5, 1e-3),
+                    reservoir=6, tau=0.8, precision="fp32"),
 }
+SCHEDULE_CACHE = os.path.join(ROOT, "paper_1806_10589_amd", "schedule_cache.txt")
 
 
 def bytes_per_lup(precision: str) -> int:
@@ -88,6 +92,121 @@ def make_workload(cfg):
                       periodic_y=True), {"porosity": phi, "spheres": nsph}
 
 
+def batch_samples(cfg):
+    """Seeded batch: edges uniform in [64, 192], porosity uniform in
+    [0.2, 0.45], Darcy velocity log-uniform in [1e-5, 1e-3]."""
+    import numpy as np
+
+    from paper_1806_10589_amd import inputs
+
+    rng = np.random.default_rng(cfg["seed"])
+    out = []
+    for i in range(cfg["batch"]):
+        n = int(rng.integers(cfg["edge"][0], cfg["edge"][1] + 1))
+        phi = float(rng.uniform(*cfg["porosity"]))
+        darcy = float(10 ** rng.uniform(np.log10(cfg["darcy"][0]), np.log10(cfg["darcy"][1])))
+        mask, ph, _ = inputs.sphere_pack(n, phi, seed=1000 * cfg["seed"] + i, reservoir_layers=cfg["reservoir"])
+        out.append((mask, dict(tau=cfg["tau"], q_target=darcy * n * n, precision=cfg["precision"]),
+                    dict(edge=n, porosity=ph, darcy=darcy)))
+    return out
+
+
+def run_batch(args, cfg):
+    import torch
+
+    from paper_1806_10589_amd import fluxlbm
+
+    t0 = time.perf_counter()
+    samples = batch_samples(cfg)
+    print(f"[bench] batch of {len(samples)} samples built in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    lats = [fluxlbm.Lattice(m, watchdog_every=1000, **kw) for m, kw, _ in samples]
+    n_total = sum(l.n_sites for l in lats)
+    b = fluxlbm.Batch(lats)
+    sched, ms_tuned = b.autotune(SCHEDULE_CACHE if os.access(os.path.dirname(SCHEDULE_CACHE), os.W_OK) else None,
+                                 trial_steps=3)
+    b.set_schedule(**dict(sched, chunk=100))
+    print(f"[bench] schedule {sched} ({ms_tuned:.3f} ms per launch while tuning)", file=sys.stderr, flush=True)
+    for l in lats:
+        l.init_equilibrium(1.0)
+    b.step(args.warmup)
+    rc, bad = b.sync()
+    if rc != fluxlbm.FLBM_OK:
+        raise SystemExit(f"unstable during warm-up (sample {bad})")
+    stream = lats[0].stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    rc, bad = b.sync()
+    mlups = n_total * args.steps / (ms_total * 1e-3) / 1e6
+    ms_kernel = b.time(args.profile_steps)
+    bpl = bytes_per_lup(cfg["precision"])
+    achieved = n_total * bpl / (ms_kernel * 1e-3) / 1e9
+    out = {
+        "metric": "MLUPS (pore sites) + HBM GB/s; steps-to-flux-tol, learned vs plain",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_total / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch64",
+            "samples": len(lats),
+            "pore_sites": n_total,
+            "edges": [x["edge"] for _, _, x in samples],
+            "tau": cfg["tau"],
+            "precision": cfg["precision"],
+            "schedule": sched,
+        },
+        "status": "ok" if rc == fluxlbm.FLBM_OK else f"unstable (sample {bad})",
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "kernel": "k_batch_step",
+            "kernel_ms": round(ms_kernel, 5),
+            "bytes_per_lup": bpl,
+        },
+    }
+    m0, kw0, _ = samples[0]
+    b.close()
+    for l in lats:
+        l.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(m0, dict(kw0, periodic_x=True, periodic_y=True), args.cpu_steps)
+        out["cpu_baseline"]["sample"] = "first sample of the batch: " + out["cpu_baseline"]["sample"]
+    print(json.dumps(out), flush=True)
+
+
+def controller_ab(max_steps=300000):
+    """Steps to |Q_out - Q*| / Q* <= 1e-3 (two-step mean, for good), plain
+    update versus the trained controller, on a held-out 128^3 pack
+    (porosity 0.25, seed 5001, tau 0.8, Darcy velocity 1e-5), same GPU."""
+    from paper_1806_10589_amd import controller
+
+    if not os.path.exists(controller.DEFAULT_WEIGHTS):
+        return None
+    params, meta = controller.load_weights()
+    mask, kw = controller.make_sample(128, 0.25, 5001, tau=0.8, darcy=1e-5)
+    r = controller.evaluate(params, mask, kw, max_steps=max_steps)
+    return {"workload": "pack128 held out (phi 0.25, seed 5001, tau 0.8, darcy 1e-5), FP32",
+            "tol": 1e-3, "plain_steps": r["plain_steps"], "learned_steps": r["learned_steps"],
+            "gain": r.get("gain"), "controller": list(r["controller"]) if r.get("controller") else None}
+
+
 def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
     from paper_1806_10589_amd import fluxlbm
 
@@ -141,6 +260,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-controller", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -153,6 +273,8 @@ def main():
     from paper_1806_10589_amd import fluxlbm
 
     cfg = CONFIGS[args.config]
+    if cfg.get("batch"):
+        return run_batch(args, cfg)
     mask, kw, info = make_workload(cfg)
     print(f"[bench] workload {args.config}: mask {mask.shape}, pore sites {(mask == 0).sum()}",
           file=sys.stderr, flush=True)
@@ -228,6 +350,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_gbs"] = round(copy_bandwidth(torch), 1)
+    if not args.no_controller:
+        out["controller_ab"] = controller_ab()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(mask, kw, args.cpu_steps)
     print(json.dumps(out), flush=True)

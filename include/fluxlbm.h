@@ -67,6 +67,7 @@ typedef int32_t flbm_status;
 /* Collision model. */
 #define FLBM_BGK 0
 #define FLBM_COLOUR 1 /* two-fluid colour-gradient model (Appendix A) */
+#define FLBM_MRT 2    /* single fluid, MRT collision of Appendix A (the paper's Sec. 3 runs) */
 
 /* Treatment of the z faces. FLBM_Z_FLUX is the paper's set-up: flux inlet at
  * z = 0, pressure outlet at z = nz-1 (Methods, last paragraph). The other two
@@ -82,7 +83,7 @@ typedef struct flbm_params {
     int32_t z_mode;             /* FLBM_Z_* */
     int32_t reservoir_layers;   /* z-planes forced to fluid at each end (pure-fluid reservoirs) */
     int32_t precision;          /* FLBM_FP64 / FLBM_FP32 / FLBM_FP16DEV */
-    int32_t model;              /* FLBM_BGK / FLBM_COLOUR */
+    int32_t model;              /* FLBM_BGK / FLBM_COLOUR / FLBM_MRT */
     int32_t watchdog_every;     /* mass, max|u| and finiteness checked at least this often (steps) */
     double tau;                 /* relaxation time, > 1/2; nu = (tau - 1/2)/3 */
     double rho0;                /* reference density of the incompressible model (eq. m357) */
@@ -254,6 +255,58 @@ flbm_status flbm_controller_state(flbm_ctx *c, int32_t *active, int32_t *release
  * aux[n][4] = {drho, rho_plain, r, offset} (FP64), decision k taken after
  * step k. Synchronises. */
 flbm_status flbm_controller_trace(flbm_ctx *c, int32_t n, float *x, double *aux);
+
+/* ---------------------------------------------------------------------
+ * Batched stepping: many lattices (porous samples of uneven size, each with
+ * its own target flux, outlet density and state) advanced together by ONE
+ * kernel launch per step. The launch walks a work list of (sample, tile
+ * range) items with a persistent grid; each sample's step is exactly what
+ * flbm_step would do (the same tile work, its own inlet sum of eq. potential
+ * in FP64, its own history and watchdog). Runs of `chunk` steps are captured
+ * as a HIP graph and replayed.
+ *
+ * The samples are ordinary contexts with device memory bound, all on the
+ * same device and stream, of one precision and one single-fluid model
+ * (FLBM_BGK or FLBM_MRT; else FLBM_EINVAL), no controller attached and not
+ * the colour model (FLBM_ESTATE). They stay usable on their own (init,
+ * targets, reads, flbm_step) and must outlive the batch. */
+typedef struct flbm_batch flbm_batch;
+
+#define FLBM_ORDER_SAMPLE 0     /* the items of one sample after another */
+#define FLBM_ORDER_INTERLEAVE 1 /* round robin over the samples */
+#define FLBM_ORDER_LARGEST 2    /* round robin, largest samples first */
+
+typedef struct flbm_schedule {
+    int32_t grid;           /* blocks of the persistent launch; 0: one block per work item */
+    int32_t order;          /* FLBM_ORDER_* */
+    int32_t tiles_per_item; /* consecutive tiles of one sample per work item (>= 1) */
+    int32_t chunk;          /* steps per captured graph (>= 1; graphs are used when even) */
+} flbm_schedule;
+
+/* samples: n context pointers (not copied beyond the call's lifetime of the
+ * array; the contexts themselves must outlive the batch). Default schedule:
+ * one block per item, interleaved, 4 tiles per item, chunk 64. */
+flbm_status flbm_batch_create(int32_t n, flbm_ctx *const *samples, flbm_batch **out);
+flbm_status flbm_batch_destroy(flbm_batch *b);
+flbm_status flbm_batch_set_schedule(flbm_batch *b, const flbm_schedule *s);
+flbm_status flbm_batch_get_schedule(const flbm_batch *b, flbm_schedule *s);
+/* n steps of every sample, asynchronous on the samples' stream */
+flbm_status flbm_batch_step(flbm_batch *b, int32_t n);
+/* synchronise; FLBM_EUNSTABLE if a sample's watchdog tripped (its index in
+ * *first_unstable, else -1) */
+flbm_status flbm_batch_sync(flbm_batch *b, int32_t *first_unstable);
+/* n steps launched one by one (no graph, no watchdog) between two HIP events
+ * on the samples' stream: the mean duration of one batched launch */
+flbm_status flbm_batch_time(flbm_batch *b, int32_t n, double *ms_per_step);
+/* Choose the schedule (persistent grid 0 / 2 / 4 / 8 / 16 blocks per compute
+ * unit, the three orders, 1 / 4 / 16 tiles per item) by timing trial_steps
+ * launches of each (1 + trial_steps steps of every sample per candidate: the
+ * samples advance), or take it from cache_path (text lines
+ * "arch precision log2(sites) grid order tiles_per_item ms"; NULL: no cache),
+ * where a new choice is appended. The chosen schedule is set. */
+flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t trial_steps, flbm_schedule *best,
+                                double *best_ms);
+const char *flbm_batch_last_error(const flbm_batch *b);
 
 /* Two-fluid colour model (Appendix A; FLBM_COLOUR contexts only, else
  * FLBM_ESTATE). The colours A (non-wetting) and B (wetting) are D3Q7

@@ -23,8 +23,8 @@ offset    delta = clip(gain (rho_hat - rho_plain), +-b rho0 |Q*| / A_in) with
           rho_plain the density eq. potential gives for the next step and
           b = trust0 max(0, 1 - n / trust_steps) after n decisions; delta = 0
           once Qbar(t - 1) has been within release_tol of Q* (relative; from
-          then on for good, and only from t >= 2), when Q* <= 0 or when
-          the offset is not finite.
+          then on for good, and only from t >= 2), when Q* <= 0, or when the
+          network output or the offset is not finite.
 """
 from __future__ import annotations
 
@@ -56,8 +56,8 @@ class OracleController:
     def _q(self, s):
         return self.qout[s] if s >= 0 else 0.0
 
-    def decide(self, orc, q_target, rho_out, rho0, a_in):
-        """Take the decision after the last recorded step; returns the offset."""
+    def inputs(self, q_target, rho_out):
+        """The 32 inputs after the recorded steps, and drho."""
         t = len(self.qout)
         qn = abs(q_target) if q_target != 0.0 else 1.0
         drho = self.rho_in[-1] - rho_out if t >= 1 else 0.0
@@ -70,23 +70,38 @@ class OracleController:
             x[31] = _f32(min(1.0, max(-1.0, math.log10(drho / self.drho_ref) / 3.0)))
         else:
             x[31] = -1.0
-        x = x.astype(np.float32).astype(np.float64)
-        y, _, _ = mlp_oracle.forward(self.params, x[None, :], bf16=True)
+        return x.astype(np.float32).astype(np.float64), drho
+
+    def network(self, x):
+        y, _, _ = mlp_oracle.forward(self.params, np.asarray(x, np.float64)[None, :], bf16=True)
+        return float(y[0])
+
+    def offset(self, y, rho_plain, n, released, *, q_target, rho_out, rho0, a_in):
+        """The offset for network output y after n decisions."""
+        qn = abs(q_target) if q_target != 0.0 else 1.0
+        b = self.trust0 * max(0.0, 1.0 - n / self.trust_steps) if self.trust_steps > 0 else 0.0
+        limit = b * rho0 * qn / a_in
+        r = min(4.0, max(-4.0, y))
+        rho_hat = rho_out + self.drho_ref * math.exp(r)
+        delta = self.gain * (rho_hat - rho_plain)
+        if not math.isfinite(y) or not math.isfinite(delta) or not q_target > 0.0 or released:
+            delta = 0.0
+        return min(limit, max(-limit, delta))
+
+    def decide(self, orc, q_target, rho_out, rho0, a_in):
+        """Take the decision after the last recorded step; returns the offset."""
+        t = len(self.qout)
+        qn = abs(q_target) if q_target != 0.0 else 1.0
+        x, drho = self.inputs(q_target, rho_out)
+        y = self.network(x)
         e2 = abs(0.5 * (self._q(t - 1) + self._q(t - 2)) - q_target) / qn
         if t >= 2 and e2 <= self.release_tol:
             self.released = True
-        n = self.decisions
-        b = self.trust0 * max(0.0, 1.0 - n / self.trust_steps) if self.trust_steps > 0 else 0.0
-        limit = b * rho0 * qn / a_in
         rho_plain = orc.plain_inlet_density()
-        r = min(4.0, max(-4.0, float(y[0])))
-        rho_hat = rho_out + self.drho_ref * math.exp(r)
-        delta = self.gain * (rho_hat - rho_plain)
-        if not math.isfinite(delta) or not q_target > 0.0 or self.released:
-            delta = 0.0
-        delta = min(limit, max(-limit, delta))
+        delta = self.offset(y, rho_plain, self.decisions, self.released, q_target=q_target, rho_out=rho_out,
+                            rho0=rho0, a_in=a_in)
         self.decisions += 1
-        self.records.append((x, drho, rho_plain, float(y[0]), delta))
+        self.records.append((x, drho, rho_plain, y, delta))
         return delta
 
     def run(self, orc, n, *, q_target, rho_out=1.0, rho0=1.0):

@@ -97,6 +97,7 @@ typedef struct orc_lattice {
     double tau, rho0, q_target, rho_out;
     double rho_offset;    /* added to the inlet density of eq. potential (controller tests) */
     int collide;
+    int mrt;              /* 1: MRT collision of Appendix A instead of BGK */
     long ncell;
     unsigned char *solid; /* [nz][ny][nx], 1 = solid */
     double *f;            /* [cell][19], post-collision state */
@@ -488,6 +489,21 @@ static double total_mass(const orc_lattice *L, const double *a, int nq)
     return m;
 }
 
+void orc_mrt_collide_site(double *f, double rho0, double tau, double alpha, double gx, double gy,
+                          double gz);
+
+/* Single-fluid MRT collision (Appendix A without the interfacial stress) of
+ * every pore cell of the streamed values. */
+static void collide_mrt(orc_lattice *L)
+{
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < L->nz; ++z)
+        for (long c = (long)z * L->ny * L->nx; c < (long)(z + 1) * L->ny * L->nx; ++c)
+            if (!L->solid[c]) orc_mrt_collide_site(&L->ft[c * Q19], L->rho0, L->tau, 0.0, 0.0, 0.0, 0.0);
+}
+
+void orc_set_mrt(orc_lattice *L, int on) { L->mrt = on; }
+
 /* One time step. hist (may be NULL) receives, in this order:
  * rho_in, Q_in, Q_out, total mass, max |u|.
  * Returns 0, or -1 if a slot was left unset (a streaming error). */
@@ -498,7 +514,10 @@ static int step_once(orc_lattice *L, double *hist)
     apply_momentum_bc(L, NULL, NULL, &rho_in, &q_in, &q_out);
     int bad = any_unset(L, L->ft, Q19);
     double umax = hist ? max_speed(L, L->ft) : 0.0;
-    collide_bgk(L);
+    if (L->mrt && L->collide)
+        collide_mrt(L);
+    else
+        collide_bgk(L);
     if (hist) {
         hist[0] = rho_in;
         hist[1] = q_in;

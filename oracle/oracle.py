@@ -57,6 +57,7 @@ def _load():
         lib.orc_set_target_flux.argtypes = [_p, _d]
         lib.orc_set_outlet_density.argtypes = [_p, _d]
         lib.orc_set_inlet_offset.argtypes = [_p, _d]
+        lib.orc_set_mrt.argtypes = [_p, _i]
         lib.orc_plain_inlet_density.argtypes = [_p]
         lib.orc_plain_inlet_density.restype = _d
         lib.orc_step_count.argtypes = [_p]
@@ -211,6 +212,10 @@ class OracleLattice:
 
     def set_outlet_density(self, rho: float) -> None:
         self._lib.orc_set_outlet_density(self._h, float(rho))
+
+    def set_mrt(self, on: bool) -> None:
+        """MRT collision of Appendix A (single fluid) instead of BGK."""
+        self._lib.orc_set_mrt(self._h, int(bool(on)))
 
     def set_inlet_offset(self, d: float) -> None:
         """Offset added to the inlet density of eq. potential (controller tests)."""

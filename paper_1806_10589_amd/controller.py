@@ -127,15 +127,17 @@ def make_sample(n: int, porosity: float, seed: int, *, tau: float, darcy: float,
 
 
 def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_margin=2000,
-        max_steps=400000, chunk=4096, record=False, settle_tol=None, settings=None):
+        max_steps=400000, chunk=4096, record=False, settle_tol=None, settings=None, ref_scale=1.0):
     """Run from rest until the two-step mean outlet error has stayed within
     ``settle_tol`` (default tol) for max(min_margin, margin_frac * t) steps.
 
     With a network the controller is attached: active (trust0 from the
     settings) or observing (trust0 = 0: the plain method exactly, inputs
-    recorded). Returns a dict with steps_to_tol, the history (rho_in, Q_in,
-    Q_out per step) and, with ``record``, the network inputs and the
-    controller's (drho, rho_plain, r, offset) per step.
+    recorded). ``ref_scale`` multiplies the reference density difference
+    (training augmentation: the network must not trust the reference).
+    Returns a dict with steps_to_tol, the history (rho_in, Q_in, Q_out per
+    step) and, with ``record``, the network inputs and the controller's
+    (drho, rho_plain, r, offset) per step.
     """
     s = dict(DEFAULTS, **(settings or {}))
     settle_tol = tol if settle_tol is None else settle_tol
@@ -144,6 +146,7 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
         lat.init_equilibrium()
         geom, drho_ref = geometry_features(mask, tau=kw["tau"], q_target=kw["q_target"],
                                            reservoir_layers=kw.get("reservoir_layers", RESERVOIR))
+        drho_ref *= ref_scale
         nz = mask.shape[0]
         if net is not None:
             lat.set_controller(net, geom, drho_ref=drho_ref, gain=s["gain"],
@@ -240,54 +243,79 @@ def train_network(net, X, T, *, steps, batch=1024, lr=2e-3, lr_end=1e-4, seed=0,
     return losses
 
 
-def train(out_path: str, *, samples: int = 40, dagger_rounds: int = 2, steps: int = 4000,
-          rows_per_run: int = 600, seed: int = 7, log=print, settings=None):
+def shift_reference(x: np.ndarray, log_scale: float) -> np.ndarray:
+    """Inputs as they would read with the reference density difference
+    multiplied by exp(log_scale): only input 31 (clipped to [-1, 1]) moves."""
+    x = x.copy()
+    x[:, 31] = np.clip(x[:, 31] - log_scale / (3.0 * math.log(10.0)), -1.0, 1.0)
+    return x
+
+
+def train(out_path: str, *, samples: int = 48, dagger_rounds: int = 3, steps: int = 6000,
+          rows_per_run: int = 600, augment: int = 4, ref_spread: float = 1.0, seed: int = 7, log=print,
+          settings=None):
+    """Train on plain-method runs of the training family, then on runs under
+    the network's own control (DAgger), all labelled with the steady density
+    of the plain run. Every run uses a reference density difference scaled
+    by a random factor exp(U[-ref_spread, ref_spread]) (the label moves with
+    it), so the network must read the steady density off the dynamics rather
+    than off the Kozeny-Carman reference or the sample's statistics."""
     import torch
 
     dev = torch.device("cuda:0")
+    rng = np.random.default_rng(seed)
     fam = training_family(samples)
     net = fluxlbm.Mlp(4096)
     net.set_params(init_params(seed))
-    Xs, Ts, info = [], [], []
+    Xs, Ts, info, cases = [], [], [], []
     # plain runs (observing controller): steady density and the inputs of every step
-    cases = []
     for i, c in enumerate(fam):
         mask, kw = make_sample(c["n"], c["porosity"], c["seed"], tau=c["tau"], darcy=c["darcy"])
         res = run(mask, kw, net=net, active=False, record=True, settle_tol=1e-4, max_steps=12 * c["n"] ** 2)
         rho_inf = steady_density(res)
         lab = label(rho_inf, res["drho_ref"])
-        rows = pick_rows(len(res["x"]), rows_per_run, seed + i)
-        Xs.append(res["x"][rows])
-        Ts.append(np.full(len(rows), lab, np.float32))
-        cases.append((mask, kw, lab, c))
+        for a in range(augment):
+            ls = 0.0 if a == 0 else float(rng.uniform(-ref_spread, ref_spread))
+            rows = pick_rows(len(res["x"]), rows_per_run, seed + 97 * i + a)
+            Xs.append(shift_reference(res["x"][rows], ls))
+            Ts.append(np.full(len(rows), np.clip(lab - ls, -4.0, 4.0), np.float32))
+        cases.append((mask, kw, rho_inf, c))
         info.append(dict(c, plain_steps_to_tol=res["steps_to_tol"], label=lab, steps=res["steps"]))
         log(f"plain {i}: n={c['n']} phi={c['porosity']:.3f} tau={c['tau']:.2f} darcy={c['darcy']:.2e} "
             f"steps_to_tol={res['steps_to_tol']} label={lab:.3f} ({res['secs']:.1f}s)")
 
     def fit(tag):
-        X = torch.from_numpy(np.concatenate(Xs)).to(dev)
-        T = torch.from_numpy(np.concatenate(Ts)).to(dev)
+        X = torch.from_numpy(np.concatenate(Xs).astype(np.float32)).to(dev)
+        T = torch.from_numpy(np.concatenate(Ts).astype(np.float32)).to(dev)
         log(f"{tag}: {X.shape[0]} rows")
         return train_network(net, X, T, steps=steps, seed=seed, log=log)
 
     losses = fit("fit 0")
     # DAgger: inputs met under the network's own control, labelled with the
-    # same steady density
+    # same steady density, at a random reference scale
     for rnd in range(dagger_rounds):
-        for i, (mask, kw, lab, c) in enumerate(cases):
+        gains = []
+        for i, (mask, kw, rho_inf, c) in enumerate(cases):
+            ls = float(rng.uniform(-ref_spread, ref_spread))
             res = run(mask, kw, net=net, active=True, record=True, max_steps=12 * c["n"] ** 2,
-                      settings=settings)
+                      settings=settings, ref_scale=math.exp(ls))
+            lab = label(rho_inf, res["drho_ref"])
             rows = pick_rows(len(res["x"]), rows_per_run, seed + 1000 * (rnd + 1) + i)
             Xs.append(res["x"][rows])
             Ts.append(np.full(len(rows), lab, np.float32))
             info[i][f"learned_steps_to_tol_r{rnd}"] = res["steps_to_tol"]
-            log(f"dagger {rnd} run {i}: steps_to_tol learned={res['steps_to_tol']} "
-                f"plain={info[i]['plain_steps_to_tol']}")
+            p = info[i]["plain_steps_to_tol"]
+            if p and res["steps_to_tol"]:
+                gains.append(p / res["steps_to_tol"])
+            log(f"dagger {rnd} run {i}: ref x{math.exp(ls):.2f} steps_to_tol learned={res['steps_to_tol']} "
+                f"plain={p}")
+        if gains:
+            log(f"dagger {rnd}: geometric-mean gain {math.exp(np.mean(np.log(gains))):.3f} over {len(gains)} runs")
         losses = fit(f"fit {rnd + 1}")
     params = net.get_params()
     meta = dict(samples=samples, dagger_rounds=dagger_rounds, steps=steps, rows_per_run=rows_per_run,
-                seed=seed, settings=dict(DEFAULTS, **(settings or {})), final_loss=losses[-1][1],
-                family=info)
+                augment=augment, ref_spread=ref_spread, seed=seed, settings=dict(DEFAULTS, **(settings or {})),
+                final_loss=losses[-1][1], family=info)
     np.savez(out_path, params=params, meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
     net.close()
     return meta
@@ -322,9 +350,11 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
     t.add_argument("--out", default=DEFAULT_WEIGHTS)
-    t.add_argument("--samples", type=int, default=40)
-    t.add_argument("--dagger", type=int, default=2)
-    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--samples", type=int, default=48)
+    t.add_argument("--dagger", type=int, default=3)
+    t.add_argument("--steps", type=int, default=6000)
+    t.add_argument("--augment", type=int, default=4)
+    t.add_argument("--ref-spread", type=float, default=1.0)
     t.add_argument("--seed", type=int, default=7)
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
@@ -338,7 +368,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "train":
         meta = train(a.out, samples=a.samples, dagger_rounds=a.dagger, steps=a.steps, seed=a.seed,
-                     log=lambda m: print(m, flush=True))
+                     augment=a.augment, ref_spread=a.ref_spread, log=lambda m: print(m, flush=True))
         print(json.dumps({"final_loss": meta["final_loss"]}))
     else:
         params, meta = load_weights(a.weights)

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -308,25 +309,35 @@ void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
         hipLaunchKernelGGL((k_colour<T, false>), dim3(c->tiles), dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
 }
 
-// The fused kernel in its four variants: with or without the watchdog
-// partials; buffer instructions (buffers below 4 GiB) or 64-bit addressing.
+// The fused kernel in its variants: with or without the watchdog partials;
+// buffer instructions (buffers below 4 GiB) or 64-bit addressing; BGK or
+// single-fluid MRT collision.
+template <typename T, bool MRT>
+void launch_stream_collide_c(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bool obs, const StepArgs &a)
+{
+    const dim3 grid(c->tiles), block(SC_BLOCK);
+    if (c->use_buf) {
+        if (obs)
+            hipLaunchKernelGGL((k_stream_collide<T, true, true, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+        else
+            hipLaunchKernelGGL((k_stream_collide<T, false, true, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+    } else {
+        if (obs)
+            hipLaunchKernelGGL((k_stream_collide<T, true, false, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+        else
+            hipLaunchKernelGGL((k_stream_collide<T, false, false, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+    }
+}
+
 template <typename T>
 void launch_stream_collide(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bool obs)
 {
     StepArgs a = step_args(c);
     a.rd = fin == (const T *)c->f[1] ? 1 : 0;
-    const dim3 grid(c->tiles), block(SC_BLOCK);
-    if (c->use_buf) {
-        if (obs)
-            hipLaunchKernelGGL((k_stream_collide<T, true, true>), grid, block, 0, s, fin, fout, c->nbr, a);
-        else
-            hipLaunchKernelGGL((k_stream_collide<T, false, true>), grid, block, 0, s, fin, fout, c->nbr, a);
-    } else {
-        if (obs)
-            hipLaunchKernelGGL((k_stream_collide<T, true, false>), grid, block, 0, s, fin, fout, c->nbr, a);
-        else
-            hipLaunchKernelGGL((k_stream_collide<T, false, false>), grid, block, 0, s, fin, fout, c->nbr, a);
-    }
+    if (c->p.model == FLBM_MRT)
+        launch_stream_collide_c<T, true>(c, s, fin, fout, obs, a);
+    else
+        launch_stream_collide_c<T, false>(c, s, fin, fout, obs, a);
 }
 
 // Enqueue one step from buffer `from` on stream s.
@@ -423,7 +434,9 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
         const double r = fmin(4.0, fmax(-4.0, (double)y));
         const double rho_hat = 1.0 + st->drho_out + c.drho_ref * exp(r);
         double delta = c.gain * (rho_hat - rho_plain);
-        if (!isfinite(delta) || !(qs > 0.0) || st->ctrl_released) delta = 0.0;
+        // a non-finite output is dropped before clipping (fmin/fmax would
+        // turn a NaN into a bound)
+        if (!isfinite(y) || !isfinite(delta) || !(qs > 0.0) || st->ctrl_released) delta = 0.0;
         delta = fmin(limit, fmax(-limit, delta));
         st->ctrl_delta = delta;
         st->ctrl_steps = n + 1;
@@ -587,7 +600,8 @@ flbm_status check_params(const flbm_params *p, std::string &why)
         return why = "unknown precision", FLBM_EINVAL;
     if (p->model == FLBM_COLOUR && p->precision == FLBM_FP16DEV)
         return why = "the colour model stores FP32 or FP64", FLBM_EINVAL;
-    if (p->model != FLBM_BGK && p->model != FLBM_COLOUR) return why = "unknown model", FLBM_EINVAL;
+    if (p->model != FLBM_BGK && p->model != FLBM_COLOUR && p->model != FLBM_MRT)
+        return why = "unknown model", FLBM_EINVAL;
     if (p->model == FLBM_COLOUR && (!std::isfinite(p->alpha) || !std::isfinite(p->beta) ||
                                     !std::isfinite(p->phi_solid)))
         return why = "colour parameters must be finite", FLBM_EINVAL;
@@ -1276,5 +1290,401 @@ const char *flbm_status_string(flbm_status s)
 }
 
 const char *flbm_last_error(const flbm_ctx *c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ======================================================================
+// Batched stepping of many lattices (samples of uneven size, each with its
+// own target flux, outlet density and state) by one launch per step.
+
+struct flbm_batch {
+    std::vector<flbm_ctx *> s;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int device = 0;
+    bool use_buf = false;
+    int precision = 0, model = 0;
+    flbm_schedule sched{};
+    BatchSample *d_tab = nullptr;
+    BatchItem *d_work = nullptr;
+    int n_work = 0, work_cap = 0;
+    std::vector<BatchSample> tab_host;   // last uploaded table
+    hipGraphExec_t graph = nullptr;
+    std::string err;
+};
+
+namespace {
+
+flbm_status bfail(flbm_batch *b, flbm_status s, const std::string &msg)
+{
+    b->err = msg;
+    return s;
+}
+
+#define BHIPCHK(b, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return bfail((b), FLBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+void batch_drop_graph(flbm_batch *b)
+{
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+}
+
+// Work list in the schedule's order.
+flbm_status batch_build_work(flbm_batch *b)
+{
+    const int tpi = std::max(1, b->sched.tiles_per_item);
+    const int ns = (int)b->s.size();
+    std::vector<std::vector<BatchItem>> per(ns);
+    for (int i = 0; i < ns; ++i)
+        for (int t = 0; t < b->s[i]->tiles; t += tpi)
+            per[i].push_back(BatchItem{i, t, std::min(t + tpi, b->s[i]->tiles), 0});
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    if (b->sched.order == FLBM_ORDER_LARGEST)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return b->s[x]->tiles > b->s[y]->tiles; });
+    std::vector<BatchItem> work;
+    if (b->sched.order == FLBM_ORDER_SAMPLE) {
+        for (int i : order) work.insert(work.end(), per[i].begin(), per[i].end());
+    } else {
+        size_t longest = 0;
+        for (auto &v : per) longest = std::max(longest, v.size());
+        for (size_t k = 0; k < longest; ++k)
+            for (int i : order)
+                if (k < per[i].size()) work.push_back(per[i][k]);
+    }
+    if ((int)work.size() > b->work_cap) {
+        if (b->d_work) (void)hipFree(b->d_work);
+        b->d_work = nullptr;
+        BHIPCHK(b, hipMalloc(&b->d_work, work.size() * sizeof(BatchItem)));
+        b->work_cap = (int)work.size();
+    }
+    BHIPCHK(b, hipMemcpy(b->d_work, work.data(), work.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    b->n_work = (int)work.size();
+    batch_drop_graph(b);
+    return FLBM_OK;
+}
+
+// Per-sample table relative to each sample's current buffer; uploaded only
+// when it changed (an odd number of steps flips every sample's buffers).
+flbm_status batch_refresh(flbm_batch *b)
+{
+    std::vector<BatchSample> t(b->s.size());
+    for (size_t i = 0; i < b->s.size(); ++i) {
+        flbm_ctx *c = b->s[i];
+        flbm_status rc = refresh_inlet_sum(c);
+        if (rc) return bfail(b, rc, "sample " + std::to_string(i) + ": " + c->err);
+        std::memset(&t[i], 0, sizeof(BatchSample));
+        t[i].a = step_args(c);
+        t[i].a.rd = c->cur;
+        t[i].f0 = c->f[c->cur];
+        t[i].f1 = c->f[c->cur ^ 1];
+        t[i].nbr = c->nbr;
+    }
+    if (t.size() != b->tab_host.size() ||
+        std::memcmp(t.data(), b->tab_host.data(), t.size() * sizeof(BatchSample)) != 0) {
+        BHIPCHK(b, hipMemcpyAsync(b->d_tab, t.data(), t.size() * sizeof(BatchSample), hipMemcpyHostToDevice,
+                                  b->stream));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));  // the host copy must outlive the transfer
+        b->tab_host = std::move(t);
+    }
+    return FLBM_OK;
+}
+
+template <typename T, bool MRT>
+void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
+{
+    const int grid = b->sched.grid > 0 ? std::min(b->sched.grid, b->n_work) : b->n_work;
+    if (b->use_buf) {
+        if (obs)
+            hipLaunchKernelGGL((k_batch_step<T, true, true, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
+                               b->d_work, b->n_work, parity);
+        else
+            hipLaunchKernelGGL((k_batch_step<T, false, true, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
+                               b->d_work, b->n_work, parity);
+    } else {
+        if (obs)
+            hipLaunchKernelGGL((k_batch_step<T, true, false, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
+                               b->d_work, b->n_work, parity);
+        else
+            hipLaunchKernelGGL((k_batch_step<T, false, false, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
+                               b->d_work, b->n_work, parity);
+    }
+    if (obs)
+        for (flbm_ctx *c : b->s)
+            hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
+}
+
+void batch_launch(flbm_batch *b, hipStream_t s, int parity, bool obs)
+{
+    flbm_ctx *c0 = b->s[0];
+    const bool mrt = b->model == FLBM_MRT;
+    with_storage(c0, [&](auto tag) {
+        using T = decltype(tag);
+        if (mrt)
+            batch_launch_t<T, true>(b, s, parity, obs);
+        else
+            batch_launch_t<T, false>(b, s, parity, obs);
+    });
+}
+
+flbm_status batch_capture(flbm_batch *b)
+{
+    if (!b->cap_stream) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    BHIPCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < b->sched.chunk; ++i) batch_launch(b, b->cap_stream, i & 1, i == b->sched.chunk - 1);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (e != hipSuccess) return bfail(b, FLBM_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return bfail(b, FLBM_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return FLBM_OK;
+}
+
+void batch_advance(flbm_batch *b, int k)
+{
+    for (flbm_ctx *c : b->s) {
+        c->steps += k;
+        c->cur ^= (k & 1);
+    }
+}
+
+flbm_status batch_check_schedule(const flbm_schedule *s)
+{
+    if (!s || s->grid < 0 || s->tiles_per_item < 1 || s->chunk < 1 || s->order < FLBM_ORDER_SAMPLE ||
+        s->order > FLBM_ORDER_LARGEST)
+        return FLBM_EINVAL;
+    return FLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+flbm_status flbm_batch_create(int32_t n, flbm_ctx *const *samples, flbm_batch **out)
+{
+    if (!out || n < 1 || !samples) return FLBM_EINVAL;
+    *out = nullptr;
+    for (int32_t i = 0; i < n; ++i)
+        if (!samples[i]) return FLBM_EINVAL;
+    flbm_ctx *c0 = samples[0];
+    for (int32_t i = 0; i < n; ++i) {
+        flbm_ctx *c = samples[i];
+        if (ensure_device(c)) return FLBM_ENOMEM;
+        if (c->stream != c0->stream || c->device != c0->device) return FLBM_EINVAL;
+        if (c->p.precision != c0->p.precision || c->p.model != c0->p.model || c->use_buf != c0->use_buf)
+            return FLBM_EINVAL;
+        if (c->colour || c->ctrl_on) return FLBM_ESTATE;
+        for (int32_t j = 0; j < i; ++j)
+            if (samples[j] == c) return FLBM_EINVAL;
+    }
+    flbm_batch *b = new (std::nothrow) flbm_batch();
+    if (!b) return FLBM_ENOMEM;
+    b->s.assign(samples, samples + n);
+    b->stream = c0->stream;
+    b->device = c0->device;
+    b->use_buf = c0->use_buf;
+    b->precision = c0->p.precision;
+    b->model = c0->p.model;
+    b->sched = flbm_schedule{0, FLBM_ORDER_INTERLEAVE, 4, 64};
+    if (hipSetDevice(b->device) != hipSuccess || hipMalloc(&b->d_tab, n * sizeof(BatchSample)) != hipSuccess) {
+        delete b;
+        return FLBM_ENOMEM;
+    }
+    if (batch_build_work(b) != FLBM_OK) {
+        (void)hipFree(b->d_tab);
+        if (b->d_work) (void)hipFree(b->d_work);
+        delete b;
+        return FLBM_EHIP;
+    }
+    *out = b;
+    return FLBM_OK;
+}
+
+flbm_status flbm_batch_destroy(flbm_batch *b)
+{
+    if (!b) return FLBM_EINVAL;
+    (void)hipSetDevice(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_tab) (void)hipFree(b->d_tab);
+    if (b->d_work) (void)hipFree(b->d_work);
+    delete b;
+    return FLBM_OK;
+}
+
+flbm_status flbm_batch_set_schedule(flbm_batch *b, const flbm_schedule *s)
+{
+    if (!b || batch_check_schedule(s)) return FLBM_EINVAL;
+    BHIPCHK(b, hipSetDevice(b->device));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->sched = *s;
+    return batch_build_work(b);
+}
+
+flbm_status flbm_batch_get_schedule(const flbm_batch *b, flbm_schedule *s)
+{
+    if (!b || !s) return FLBM_EINVAL;
+    *s = b->sched;
+    return FLBM_OK;
+}
+
+flbm_status flbm_batch_step(flbm_batch *b, int32_t n)
+{
+    if (!b || n < 0) return FLBM_EINVAL;
+    if (n == 0) return FLBM_OK;
+    BHIPCHK(b, hipSetDevice(b->device));
+    flbm_status rc = batch_refresh(b);
+    if (rc) return rc;
+    int32_t left = n;
+    int parity = 0;
+    while (left > 0) {
+        if (left >= b->sched.chunk && (b->sched.chunk & 1) == 0) {
+            // a graph of an even number of steps starts and ends at parity 0
+            if (!b->graph) {
+                rc = batch_capture(b);
+                if (rc) return rc;
+            }
+            BHIPCHK(b, hipGraphLaunch(b->graph, b->stream));
+            left -= b->sched.chunk;
+        } else {
+            const int k = std::min(left, b->sched.chunk);
+            for (int i = 0; i < k; ++i) batch_launch(b, b->stream, (parity + i) & 1, i == k - 1);
+            BHIPCHK(b, hipGetLastError());
+            parity = (parity + k) & 1;
+            left -= k;
+        }
+    }
+    batch_advance(b, n);
+    return FLBM_OK;
+}
+
+flbm_status flbm_batch_sync(flbm_batch *b, int32_t *first_unstable)
+{
+    if (!b) return FLBM_EINVAL;
+    if (first_unstable) *first_unstable = -1;
+    BHIPCHK(b, hipSetDevice(b->device));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->s.size(); ++i) {
+        uint32_t u = 0;
+        BHIPCHK(b, hipMemcpy(&u, &b->s[i]->st->unstable, sizeof(u), hipMemcpyDeviceToHost));
+        if (u) {
+            if (first_unstable) *first_unstable = (int32_t)i;
+            return bfail(b, FLBM_EUNSTABLE, "watchdog tripped in sample " + std::to_string(i));
+        }
+    }
+    return FLBM_OK;
+}
+
+flbm_status flbm_batch_time(flbm_batch *b, int32_t n, double *ms_per_step)
+{
+    if (!b || n < 1 || !ms_per_step) return FLBM_EINVAL;
+    BHIPCHK(b, hipSetDevice(b->device));
+    flbm_status rc = batch_refresh(b);
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    BHIPCHK(b, hipEventRecord(e0, b->stream));
+    for (int i = 0; i < n; ++i) batch_launch(b, b->stream, i & 1, false);
+    BHIPCHK(b, hipEventRecord(e1, b->stream));
+    BHIPCHK(b, hipEventSynchronize(e1));
+    float ms = 0.f;
+    BHIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    batch_advance(b, n);
+    *ms_per_step = (double)ms / n;
+    return FLBM_OK;
+}
+
+flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t trial_steps, flbm_schedule *best,
+                                double *best_ms)
+{
+    if (!b || trial_steps < 1) return FLBM_EINVAL;
+    BHIPCHK(b, hipSetDevice(b->device));
+    hipDeviceProp_t prop;
+    BHIPCHK(b, hipGetDeviceProperties(&prop, b->device));
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    int64_t sites = 0;
+    for (flbm_ctx *c : b->s) sites += c->lat.n;
+    int bucket = 0;
+    while ((int64_t{1} << (bucket + 1)) <= sites) ++bucket;
+    const int prec = b->precision;
+    const std::string key = arch + " " + std::to_string(prec) + " " + std::to_string(bucket);
+    const int chunk = b->sched.chunk;
+    // a cached choice for this architecture, precision and size bucket
+    if (cache_path) {
+        FILE *fp = std::fopen(cache_path, "r");
+        if (fp) {
+            char a[64];
+            int p, bk, g, o, t;
+            double ms;
+            while (std::fscanf(fp, "%63s %d %d %d %d %d %lf", a, &p, &bk, &g, &o, &t, &ms) == 7) {
+                if (arch == a && p == prec && bk == bucket) {
+                    std::fclose(fp);
+                    flbm_schedule s{g, o, t, chunk};
+                    flbm_status rc = flbm_batch_set_schedule(b, &s);
+                    if (rc) return rc;
+                    if (best) *best = s;
+                    if (best_ms) *best_ms = ms;
+                    return FLBM_OK;
+                }
+            }
+            std::fclose(fp);
+        }
+    }
+    const int cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    const int grids[] = {0, 2 * cus, 4 * cus, 8 * cus, 16 * cus};
+    const int orders[] = {FLBM_ORDER_SAMPLE, FLBM_ORDER_INTERLEAVE, FLBM_ORDER_LARGEST};
+    const int tpis[] = {1, 4, 16};
+    flbm_schedule bs = b->sched;
+    double bms = 1e300;
+    for (int g : grids)
+        for (int o : orders)
+            for (int t : tpis) {
+                flbm_schedule s{g, o, t, chunk};
+                flbm_status rc = flbm_batch_set_schedule(b, &s);
+                if (rc) return rc;
+                double ms = 0.0;
+                rc = flbm_batch_time(b, 1, &ms);  // warm-up
+                if (rc) return rc;
+                rc = flbm_batch_time(b, trial_steps, &ms);
+                if (rc) return rc;
+                if (ms < bms) {
+                    bms = ms;
+                    bs = s;
+                }
+            }
+    flbm_status rc = flbm_batch_set_schedule(b, &bs);
+    if (rc) return rc;
+    if (cache_path) {
+        FILE *fp = std::fopen(cache_path, "a");
+        if (fp) {
+            std::fprintf(fp, "%s %d %d %d %d %d %.6f\n", arch.c_str(), prec, bucket, bs.grid, bs.order,
+                         bs.tiles_per_item, bms);
+            std::fclose(fp);
+        }
+    }
+    if (best) *best = bs;
+    if (best_ms) *best_ms = bms;
+    return FLBM_OK;
+}
+
+const char *flbm_batch_last_error(const flbm_batch *b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

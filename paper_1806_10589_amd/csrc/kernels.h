@@ -12,6 +12,7 @@
 #include <stdint.h>
 
 #include "d3q19.h"
+#include "mrt.h"
 
 namespace flbm {
 
@@ -575,15 +576,16 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
 // boundary sites also reduce sum u_z (FP64) and the last of them records Q_in,
 // Q_out and advances the step counter.
 // OBS: also write per-tile partials of mass, max |u|^2 and a non-finite flag.
-template <typename T, bool OBS, bool BUF>
-__global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict__ fin,
-                                                             T *__restrict__ fout,
-                                                             const int32_t *__restrict__ nbr,
-                                                             StepArgs a)
+// The work of one tile (SC_BLOCK threads), shared by the single-lattice
+// kernel (one tile per block) and the batched kernel (a work list of tiles
+// of many lattices per block).
+template <typename T, bool OBS, bool BUF, bool MRT>
+__device__ __forceinline__ void stream_collide_tile(const int tile, const T *__restrict__ fin,
+                                                    T *__restrict__ fout, const int32_t *__restrict__ nbr,
+                                                    const StepArgs &a)
 {
     using R = typename Compute<T>::type;
     constexpr int V = SC_V;
-    const int tile = (int)blockIdx.x;
     const int64_t s0 = ((int64_t)tile * SC_BLOCK + threadIdx.x) * V;
     const int64_t npad = a.npad;
 
@@ -646,7 +648,15 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         R drho, ux, uy, uz;
-        bgk_collide(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
+        if constexpr (MRT) {
+            if (omega != (R)0) {
+                mrt_collide<false>(g[v], omega, (R)a.rho0, (R)a.inv_rho0, (R)0, (R)0, (R)0, (R)0, drho, ux, uy, uz);
+            } else {
+                bgk_collide(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
+            }
+        } else {
+            bgk_collide(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
+        }
         if (OBS) {
             m += (double)drho;
             u2max = fmaxf(u2max, (float)(ux * ux + uy * uy + uz * uz));
@@ -694,6 +704,49 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
     }
 
     step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a);
+}
+
+template <typename T, bool OBS, bool BUF, bool MRT = false>
+__global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict__ fin,
+                                                             T *__restrict__ fout,
+                                                             const int32_t *__restrict__ nbr,
+                                                             StepArgs a)
+{
+    stream_collide_tile<T, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a);
+}
+
+// Batched step: many lattices in one launch. Each lattice keeps its own
+// buffers, pull table, state and partials (its StepArgs); a work list of
+// (lattice, tile range) items is walked by a persistent grid, block b taking
+// items b, b + gridDim.x, ... Every tile does exactly the single-lattice work,
+// so each lattice's step is the same as a launch of its own.
+struct BatchSample {
+    StepArgs a;                 // rd holds the slot read at batch parity 0
+    const void *f0, *f1;        // f0: the buffer read at batch parity 0
+    const int32_t *nbr;
+};
+
+struct BatchItem {
+    int32_t sample, t0, t1, pad_;
+};
+
+template <typename T, bool OBS, bool BUF, bool MRT>
+__global__ __launch_bounds__(SC_BLOCK) void k_batch_step(const BatchSample *__restrict__ tab,
+                                                         const BatchItem *__restrict__ work, int32_t n_work,
+                                                         int32_t parity)
+{
+    for (int w = (int)blockIdx.x; w < n_work; w += (int)gridDim.x) {
+        const BatchItem it = work[w];
+        const BatchSample *S = tab + it.sample;
+        StepArgs a = S->a;
+        a.rd ^= parity;
+        const T *fin = (const T *)(parity ? S->f1 : S->f0);
+        T *fout = (T *)(parity ? S->f0 : S->f1);
+        for (int t = it.t0; t < it.t1; ++t) {
+            stream_collide_tile<T, OBS, BUF, MRT>(t, fin, fout, S->nbr, a);
+            __syncthreads();  // the tile's LDS reductions are reused by the next tile
+        }
+    }
 }
 
 // Reduce the per-tile observables of the last step into its history record

@@ -26,11 +26,11 @@ FLBM_EBOUND = -7
 FLBM_ESTATE = -8
 
 FLBM_FP64, FLBM_FP32, FLBM_FP16DEV = 0, 1, 2
-FLBM_BGK, FLBM_COLOUR = 0, 1
+FLBM_BGK, FLBM_COLOUR, FLBM_MRT = 0, 1, 2
 FLBM_Z_FLUX, FLBM_Z_PERIODIC, FLBM_Z_WALL = 0, 1, 2
 
 PRECISIONS = {"fp64": FLBM_FP64, "fp32": FLBM_FP32, "fp16dev": FLBM_FP16DEV}
-MODELS = {"bgk": FLBM_BGK, "colour": FLBM_COLOUR}
+MODELS = {"bgk": FLBM_BGK, "colour": FLBM_COLOUR, "mrt": FLBM_MRT}
 
 
 class FlbmError(RuntimeError):
@@ -48,6 +48,14 @@ class flbm_controller_params(ctypes.Structure):
         ("drho_ref", ctypes.c_double), ("gain", ctypes.c_double), ("trust0", ctypes.c_double), ("release_tol", ctypes.c_double),
         ("trust_steps", ctypes.c_int32), ("reserved2", ctypes.c_int32),
     ]
+
+
+class flbm_schedule(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("order", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32),
+                ("chunk", ctypes.c_int32)]
+
+
+FLBM_ORDER_SAMPLE, FLBM_ORDER_INTERLEAVE, FLBM_ORDER_LARGEST = 0, 1, 2
 
 
 class flbm_params(ctypes.Structure):
@@ -117,10 +125,20 @@ _SIGS = {
     "flbm_set_controller": [_P, _P, _P],
     "flbm_controller_state": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _DP, _I64P],
     "flbm_controller_trace": [_P, _I32, _P, _P],
+    "flbm_batch_create": [_I32, _P, ctypes.POINTER(_P)],
+    "flbm_batch_destroy": [_P],
+    "flbm_batch_set_schedule": [_P, _P],
+    "flbm_batch_get_schedule": [_P, _P],
+    "flbm_batch_step": [_P, _I32],
+    "flbm_batch_sync": [_P, ctypes.POINTER(_I32)],
+    "flbm_batch_time": [_P, _I32, _DP],
+    "flbm_batch_autotune": [_P, ctypes.c_char_p, _I32, _P, _DP],
+    "flbm_batch_last_error": [_P],
     "flbm_status_string": [_I32],
     "flbm_last_error": [_P],
 }
-_RESTYPES = {"flbm_status_string": ctypes.c_char_p, "flbm_last_error": ctypes.c_char_p}
+_RESTYPES = {"flbm_status_string": ctypes.c_char_p, "flbm_last_error": ctypes.c_char_p,
+             "flbm_batch_last_error": ctypes.c_char_p}
 
 _lib = None
 
@@ -418,6 +436,60 @@ def flbm_controller_trace(ctx, n: int):
     return x, aux
 
 
+def _bcheck(rc: int, where: str, b):
+    if rc != FLBM_OK:
+        lib = load_library()
+        detail = lib.flbm_status_string(rc).decode()
+        extra = lib.flbm_batch_last_error(b) if b else b""
+        if extra:
+            detail += ": " + extra.decode()
+        raise FlbmError(rc, where, detail)
+
+
+def flbm_batch_create(ctxs):
+    arr = (_P * len(ctxs))(*ctxs)
+    out = _P()
+    _bcheck(load_library().flbm_batch_create(len(ctxs), arr, ctypes.byref(out)), "flbm_batch_create", None)
+    return out.value
+
+
+def flbm_batch_destroy(b) -> None:
+    _bcheck(load_library().flbm_batch_destroy(b), "flbm_batch_destroy", None)
+
+
+def flbm_batch_set_schedule(b, sched: flbm_schedule) -> None:
+    _bcheck(load_library().flbm_batch_set_schedule(b, ctypes.byref(sched)), "flbm_batch_set_schedule", b)
+
+
+def flbm_batch_get_schedule(b) -> flbm_schedule:
+    s = flbm_schedule()
+    _bcheck(load_library().flbm_batch_get_schedule(b, ctypes.byref(s)), "flbm_batch_get_schedule", b)
+    return s
+
+
+def flbm_batch_step(b, n: int) -> None:
+    _bcheck(load_library().flbm_batch_step(b, int(n)), "flbm_batch_step", b)
+
+
+def flbm_batch_sync(b):
+    i = _I32(-1)
+    rc = load_library().flbm_batch_sync(b, ctypes.byref(i))
+    return rc, int(i.value)
+
+
+def flbm_batch_time(b, n: int) -> float:
+    ms = _D()
+    _bcheck(load_library().flbm_batch_time(b, int(n), ctypes.byref(ms)), "flbm_batch_time", b)
+    return float(ms.value)
+
+
+def flbm_batch_autotune(b, cache_path: str | None, trial_steps: int):
+    s, ms = flbm_schedule(), _D()
+    _bcheck(load_library().flbm_batch_autotune(b, cache_path.encode() if cache_path else None, int(trial_steps),
+                                               ctypes.byref(s), ctypes.byref(ms)), "flbm_batch_autotune", b)
+    return s, float(ms.value)
+
+
 # ------------------------------------------------------------------ convenience
 
 class Mlp:
@@ -641,3 +713,45 @@ class Lattice:
 
     def controller_trace(self, n):
         return flbm_controller_trace(self.ctx, n)
+
+
+class Batch:
+    """Many ``Lattice`` objects (same device, stream, precision and model)
+    stepped together by one launch per step."""
+
+    def __init__(self, lattices):
+        self.lattices = list(lattices)
+        self.handle = flbm_batch_create([l.ctx for l in self.lattices])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            flbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        flbm_batch_step(self.handle, n)
+
+    def sync(self):
+        return flbm_batch_sync(self.handle)
+
+    def time(self, n):
+        return flbm_batch_time(self.handle, n)
+
+    @property
+    def schedule(self):
+        s = flbm_batch_get_schedule(self.handle)
+        return dict(grid=s.grid, order=s.order, tiles_per_item=s.tiles_per_item, chunk=s.chunk)
+
+    def set_schedule(self, grid=0, order=FLBM_ORDER_INTERLEAVE, tiles_per_item=4, chunk=64):
+        flbm_batch_set_schedule(self.handle, flbm_schedule(grid, order, tiles_per_item, chunk))
+
+    def autotune(self, cache_path=None, trial_steps=5):
+        s, ms = flbm_batch_autotune(self.handle, cache_path, trial_steps)
+        return dict(grid=s.grid, order=s.order, tiles_per_item=s.tiles_per_item, chunk=s.chunk), ms
+

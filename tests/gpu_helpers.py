@@ -7,12 +7,14 @@ from paper_1806_10589_amd import fluxlbm, inputs
 
 
 def pair(mask, *, precision="fp64", tau=0.8, q_target=0.0, rho_out=1.0, rho0=1.0,
-         periodic_x=True, periodic_y=True, z_mode=0, watchdog_every=1000, umax_limit=0.1):
+         periodic_x=True, periodic_y=True, z_mode=0, watchdog_every=1000, umax_limit=0.1, model="bgk"):
     lat = fluxlbm.Lattice(mask, tau=tau, q_target=q_target, rho_out=rho_out, rho0=rho0,
                           precision=precision, periodic_x=periodic_x, periodic_y=periodic_y,
-                          z_mode=z_mode, watchdog_every=watchdog_every, umax_limit=umax_limit)
+                          z_mode=z_mode, watchdog_every=watchdog_every, umax_limit=umax_limit,
+                          model=model)
     orc = oracle.OracleLattice(mask, tau=tau, q_target=q_target, rho_out=rho_out, rho0=rho0,
                                periodic_x=periodic_x, periodic_y=periodic_y, z_mode=z_mode)
+    orc.set_mrt(model == "mrt")
     return lat, orc
 
 

@@ -42,7 +42,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     # compile the header with the host C compiler and compare every field
     # offset and the struct sizes with the ctypes mirrors
     structs = {"flbm_params": fluxlbm.flbm_params,
-               "flbm_controller_params": fluxlbm.flbm_controller_params}
+               "flbm_controller_params": fluxlbm.flbm_controller_params,
+               "flbm_schedule": fluxlbm.flbm_schedule}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fluxlbm.h"', "int main(void){"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')

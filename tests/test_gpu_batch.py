@@ -1,0 +1,148 @@
+"""Batched stepping: many lattices of uneven size, each with its own target
+flux, outlet density and relaxation time, advanced by one launch per step.
+Each sample must equal the same lattice stepped on its own, bit for bit
+(the same tile work in the same order), under every schedule; one sample is
+also checked against the FP64 oracle directly."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1806_10589_amd import fluxlbm, inputs
+
+from .gpu_helpers import dense_to_sites, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [  # (shape or pack edge, porosity/solid fraction, seed, tau, q, rho_out)
+    ((9, 13, 17), 0.3, 1, 0.8, 0.05, 1.0),
+    ((24, 40, 36), 0.35, 2, 0.9, 0.4, 1.001),
+    ((5, 3, 4), 0.2, 3, 0.7, 0.01, 1.0),
+    ((30, 20, 20), 0.25, 4, 1.1, 0.2, 0.999),
+    ((12, 64, 48), 0.3, 5, 0.75, 0.3, 1.0),
+]
+
+
+def _mask(shape, solid, seed):
+    m = inputs.random_mask(shape, solid, seed)
+    m[0, 0, 0] = 0
+    m[-1, 0, 0] = 0
+    return m
+
+
+def _lattices(precision, model="bgk"):
+    out = []
+    for shape, solid, seed, tau, q, rho_out in SPECS:
+        m = _mask(shape, solid, seed)
+        lat = fluxlbm.Lattice(m, precision=precision, tau=tau, q_target=q, rho_out=rho_out, model=model,
+                              watchdog_every=16)
+        lat.init_equilibrium(rho_out)
+        out.append((m, lat))
+    return out
+
+
+SCHEDULES = [
+    dict(grid=0, order=fluxlbm.FLBM_ORDER_INTERLEAVE, tiles_per_item=4, chunk=8),
+    dict(grid=3, order=fluxlbm.FLBM_ORDER_SAMPLE, tiles_per_item=1, chunk=6),
+    dict(grid=64, order=fluxlbm.FLBM_ORDER_LARGEST, tiles_per_item=3, chunk=5),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("sched", range(len(SCHEDULES)))
+def test_batch_equals_single_lattices_bitwise(precision, sched):
+    singles = _lattices(precision)
+    batched = _lattices(precision)
+    b = fluxlbm.Batch([l for _, l in batched])
+    b.set_schedule(**SCHEDULES[sched])
+    n = 37
+    b.step(n)
+    rc, bad = b.sync()
+    assert rc == fluxlbm.FLBM_OK and bad == -1
+    for (m, s), (_, l) in zip(singles, batched):
+        s.step(n)
+        assert l.step_count == n
+        assert np.array_equal(s.read_distributions(), l.read_distributions())
+        assert np.array_equal(s.history(n), l.history(n), equal_nan=True)
+    # and again from an odd parity (every sample's buffers flipped)
+    b.step(10)
+    for (m, s), (_, l) in zip(singles, batched):
+        s.step(10)
+        assert np.array_equal(s.read_distributions(), l.read_distributions())
+    b.close()
+
+
+def test_batch_mrt_equals_single():
+    singles = _lattices("fp64", "mrt")
+    batched = _lattices("fp64", "mrt")
+    b = fluxlbm.Batch([l for _, l in batched])
+    b.step(21)
+    for (m, s), (_, l) in zip(singles, batched):
+        s.step(21)
+        assert np.array_equal(s.read_distributions(), l.read_distributions())
+    b.close()
+
+
+def test_batch_sample_matches_oracle():
+    import oracle
+
+    batched = _lattices("fp64")
+    b = fluxlbm.Batch([l for _, l in batched])
+    b.step(12)
+    shape, solid, seed, tau, q, rho_out = SPECS[1]
+    m, lat = batched[1]
+    orc = oracle.OracleLattice(m, tau=tau, q_target=q, rho_out=rho_out)
+    orc.init_equilibrium(rho_out)
+    h = orc.step(12)
+    assert rel_err(lat.read_distributions(), dense_to_sites(m, orc.get_f())) <= 1e-12
+    assert np.max(np.abs(lat.history(12)[:, 2] - h[:, 2])) <= 1e-12 * max(1.0, q)
+    b.close()
+
+
+def test_batch_watchdog_names_the_sample():
+    batched = _lattices("fp64")
+    b = fluxlbm.Batch([l for _, l in batched])
+    m, lat = batched[3]
+    f = lat.read_distributions()
+    f[4, 7] = np.nan
+    lat.write_distributions(f)
+    b.step(16)
+    rc, bad = b.sync()
+    assert rc == fluxlbm.FLBM_EUNSTABLE and bad == 3
+    b.close()
+
+
+def test_batch_rejects_mixed_samples():
+    m = _mask((9, 13, 17), 0.3, 1)
+    a = fluxlbm.Lattice(m, precision="fp32", q_target=0.05)
+    c = fluxlbm.Lattice(m, precision="fp64", q_target=0.05)
+    with pytest.raises(fluxlbm.FlbmError) as e:
+        fluxlbm.Batch([a, c])
+    assert e.value.status == fluxlbm.FLBM_EINVAL
+    k = fluxlbm.Lattice(m, precision="fp32", model="colour", q_target=0.05)
+    with pytest.raises(fluxlbm.FlbmError) as e:
+        fluxlbm.Batch([a, k])
+    assert e.value.status in (fluxlbm.FLBM_EINVAL, fluxlbm.FLBM_ESTATE)
+
+
+def test_autotune_picks_and_caches_a_schedule(tmp_path):
+    batched = _lattices("fp32")
+    b = fluxlbm.Batch([l for _, l in batched])
+    cache = str(tmp_path / "sched.txt")
+    s1, ms1 = b.autotune(cache, trial_steps=2)
+    assert ms1 > 0 and s1["tiles_per_item"] in (1, 4, 16) and s1["order"] in (0, 1, 2)
+    lines = open(cache).read().split("\n")
+    assert len([l for l in lines if l.strip()]) == 1
+    s2, ms2 = b.autotune(cache, trial_steps=2)
+    assert s2 == s1 and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 1
+    # the tuned batch still steps correctly: compare with singles from here
+    singles = [fluxlbm.Lattice(m, precision="fp32", tau=t[3], q_target=t[4], rho_out=t[5])
+               for (m, _), t in zip(batched, SPECS)]
+    for s, (_, l) in zip(singles, batched):
+        s.load_state(l.save_state())
+    b.step(9)
+    for s, (_, l) in zip(singles, batched):
+        s.step(9)
+        assert np.array_equal(s.read_distributions(), l.read_distributions())
+    b.close()

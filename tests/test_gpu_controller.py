@@ -35,8 +35,7 @@ def _params(seed, b3, scale=0.3):
 GEOM = np.linspace(-0.5, 0.5, 15).astype(np.float32)
 
 
-@pytest.mark.parametrize("gain,trust0,b3", [(0.5, 2.0, 0.5), (0.2, 50.0, -0.3)])
-def test_decisions_match_oracle(gain, trust0, b3):
+def _run_pair(gain, trust0, b3, n=80):
     mask = _mask()
     q = 0.02
     lat, orc = pair(mask, precision="fp64", tau=0.9, q_target=q)
@@ -48,26 +47,60 @@ def test_decisions_match_oracle(gain, trust0, b3):
     kw = dict(drho_ref=1e-3, gain=gain, trust0=trust0, release_tol=1e-12, trust_steps=50)
     lat.set_controller(net, GEOM, **kw)
     oc = OracleController(params.astype(np.float64), GEOM, **kw)
-    n = 80
     lat.step(n)
     hg = lat.history(n)
     ho = oc.run(orc, n, q_target=q)
     x, aux = lat.controller_trace(n)
+    return lat, orc, net, oc, hg, ho, x, aux, q, kw
+
+
+def test_clipped_decisions_match_oracle_exactly():
+    # every proposal lies far above the trust bound, so each offset is the
+    # bound itself: the same FP64 number on both sides, and the two runs stay
+    # equal to rounding
+    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(1.0, 0.5, 8.0)
     xo = np.array([r[0] for r in oc.records])
     auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
     assert np.max(np.abs(x - xo)) <= 1e-6
+    assert np.max(np.abs(aux[:, 0] - auxo[:, 0])) <= 1e-12          # drho
     assert np.max(np.abs(aux[:, 1] - auxo[:, 1])) <= 1e-12          # rho_plain
     assert np.max(np.abs(aux[:, 2] - auxo[:, 2])) <= 2e-4 * max(1.0, np.abs(auxo[:, 2]).max())
-    scale = kw["drho_ref"] * math.exp(4.0) * gain
-    assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 2e-4 * scale + 1e-15   # offsets
-    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 2e-4 * scale + 1e-12      # rho_in
-    assert np.max(np.abs(hg[:, 1] - ho[:, 1])) <= 1e-9 * q + 2e-4 * scale * orc.a_in
-    # the offsets did something, and the last 30 steps are plain (bound decayed)
-    assert np.max(np.abs(auxo[:50, 3])) > 1e-6
-    assert np.all(auxo[50:, 3] == 0.0) and np.all(aux[50:, 3] == 0.0)
-    assert np.allclose(hg[51:, 1], q, rtol=1e-10)
+    limit = 0.5 * q / orc.a_in * np.maximum(0.0, 1.0 - np.arange(80) / 50.0)
+    assert np.allclose(auxo[:, 3], limit, rtol=1e-15, atol=0)        # clipped every time
+    assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 1e-15
+    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 1e-12              # rho_in
+    assert np.max(np.abs(hg[:, 2] - ho[:, 2])) <= 1e-12              # Q_out
+    assert np.allclose(hg[51:, 1], q, rtol=1e-10)                    # bound gone: plain
     active, released, _, decisions = lat.controller_state()
-    assert active and not released and decisions == n
+    assert active and not released and decisions == 80
+    lat.close()
+    net.close()
+
+
+def test_proportional_decisions_follow_the_rule():
+    # offsets inside the bound carry the network's FP32 output: check each
+    # device decision against the rule evaluated by the oracle on the
+    # device's own record, then the trajectory against the oracle run with
+    # the propagated tolerance
+    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(0.2, 50.0, -0.3)
+    a_in = orc.a_in
+    for k in range(80):
+        # inputs from the device's own history of Q_out and rho_in
+        ref = OracleController(oc.params, GEOM, **kw)
+        ref.qout = list(hg[:k + 1, 2])
+        ref.rho_in = list(hg[:k + 1, 0])
+        xk, drho = ref.inputs(q, 1.0)
+        assert np.max(np.abs(x[k] - xk)) <= 1e-6, k
+        assert abs(aux[k, 0] - drho) <= 1e-15
+        y = ref.network(x[k].astype(np.float64))
+        assert abs(aux[k, 2] - y) <= 2e-4 * max(1.0, abs(y)), k
+        d = ref.offset(aux[k, 2], aux[k, 1], k, False, q_target=q, rho_out=1.0, rho0=1.0, a_in=a_in)
+        assert abs(aux[k, 3] - d) <= 1e-15 + 1e-12 * abs(d), k
+    assert np.any(np.abs(aux[:50, 3]) > 0) and np.all(aux[50:, 3] == 0.0)
+    auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
+    scale = kw["drho_ref"] * math.exp(4.0) * kw["gain"]
+    assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 2e-4 * scale
+    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 2e-4 * scale + 1e-12
     lat.close()
     net.close()
 
