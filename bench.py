@@ -7,8 +7,14 @@ velocity 1e-4 (Q* = 1e-4 * 256^2), pressure outlet rho = 1.
 
 Prints one JSON line: MLUPS over pore sites for the timed steps, the roofline
 of the fused stream-collide kernel (algorithmic bytes per launch over its
-mean HIP-event duration), and the FP64 CPU oracle timed on a bounded sample
-of the same workload.
+mean HIP-event duration), the FP64 CPU oracle timed on a bounded sample of
+the same workload, and the learned controller's steps-to-tolerance against
+the plain update on a held-out 128^3 pack.
+
+Other workloads (``--config``): pack256h (FP16 deviation storage), pack256m
+(MRT collision), pack512 (512^3, porosity 0.25), slit (FP64 16x16x64) and
+batch64 (64 samples of uneven size in one batched launch per step, with the
+autotuned schedule).
 """
 from __future__ import annotations
 
@@ -31,6 +37,11 @@ CONFIGS = {
     "pack256": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp32"),
     "pack256h": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp16dev"),
     "pack512": dict(n=512, porosity=0.25, seed=5, reservoir=6, tau=0.8, darcy=1e-5, precision="fp32"),
+    "pack256m": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp32",
+                     model="mrt"),
+    # two-fluid colour model: non-wetting fluid in the inlet reservoir, wetting elsewhere
+    "pack256c": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp32",
+                     model="colour", alpha=0.005, beta=0.7, phi_solid=-0.5),
     "slit": dict(slit=True, tau=1.0, q=0.5, precision="fp64"),
     # 64 samples of uneven size in one batched launch per step
     "batch64": dict(batch=64, seed=3, edge=(64, 192), porosity=(0.2, 0.45), darcy=(1e-5, 1e-3),
@@ -39,11 +50,17 @@ CONFIGS = {
 SCHEDULE_CACHE = os.path.join(ROOT, "paper_1806_10589_amd", "schedule_cache.txt")
 
 
-def bytes_per_lup(precision: str) -> int:
+def bytes_per_lup(precision: str, model: str = "bgk") -> int:
     """Algorithmic bytes of one pore-site update: 19 populations read and
-    written once in the storage type, plus 18 int32 pull indices."""
+    written once in the storage type, plus 18 int32 pull indices. The colour
+    model adds, per site, the phase pass (14 D3Q7 colour values read, 6
+    indices, N_A, N_B and phi written) and, in the colour step, phi of the 18
+    neighbours, N_A, N_B and the 14 recoloured values written."""
     elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
-    return 19 * 2 * elem + 18 * 4
+    single = 19 * 2 * elem + 18 * 4
+    if model != "colour":
+        return single
+    return single + (14 * elem + 6 * 4 + 3 * elem) + (18 * elem + 2 * elem + 14 * elem)
 
 
 def kernel_source_hash() -> str:
@@ -88,8 +105,12 @@ def make_workload(cfg):
     mask, phi, nsph = inputs.sphere_pack(cfg["n"], cfg["porosity"], seed=cfg["seed"],
                                          reservoir_layers=cfg["reservoir"])
     q = cfg["darcy"] * mask.shape[1] * mask.shape[2]
-    return mask, dict(tau=cfg["tau"], q_target=q, precision=cfg["precision"], periodic_x=True,
-                      periodic_y=True), {"porosity": phi, "spheres": nsph}
+    kw = dict(tau=cfg["tau"], q_target=q, precision=cfg["precision"], periodic_x=True, periodic_y=True,
+              model=cfg.get("model", "bgk"))
+    for k in ("alpha", "beta", "phi_solid"):
+        if k in cfg:
+            kw[k] = cfg[k]
+    return mask, kw, {"porosity": phi, "spheres": nsph}
 
 
 def batch_samples(cfg):
@@ -201,7 +222,7 @@ def controller_ab(max_steps=300000):
         return None
     params, meta = controller.load_weights()
     mask, kw = controller.make_sample(128, 0.25, 5001, tau=0.8, darcy=1e-5)
-    r = controller.evaluate(params, mask, kw, max_steps=max_steps)
+    r = controller.evaluate(params, mask, kw, max_steps=max_steps, settings=controller.settings_of(meta))
     return {"workload": "pack128 held out (phi 0.25, seed 5001, tau 0.8, darcy 1e-5), FP32",
             "tol": 1e-3, "plain_steps": r["plain_steps"], "learned_steps": r["learned_steps"],
             "gain": r.get("gain"), "controller": list(r["controller"]) if r.get("controller") else None}
@@ -227,13 +248,31 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(mask, kw, steps):
-    """FP64 oracle on the same workload, `steps` steps after one warm-up step."""
+def cpu_baseline(mask, kw, steps, reservoir=6):
+    """FP64 oracle on the same workload, `steps` steps after one warm-up step
+    (the two-fluid oracle for the colour model, started from the same
+    two-layer colour state)."""
+    import numpy as np
+
     import oracle
 
-    orc = oracle.OracleLattice(mask, tau=kw["tau"], q_target=kw["q_target"], rho_out=1.0,
-                               periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
-    orc.init_equilibrium(1.0)
+    colour = kw.get("model") == "colour"
+    if colour:
+        orc = oracle.OracleColour(mask, tau=kw["tau"], alpha=kw["alpha"], beta=kw["beta"],
+                                  phi_solid=kw["phi_solid"], q_target=kw["q_target"],
+                                  periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
+        na = np.zeros(mask.shape)
+        na[:reservoir] = 1.0
+        na[mask.astype(bool)] = 0.0
+        nb = 1.0 - na
+        nb[mask.astype(bool)] = 0.0
+        orc.init(na, nb)
+        steps = max(1, steps // 4)
+    else:
+        orc = oracle.OracleLattice(mask, tau=kw["tau"], q_target=kw["q_target"], rho_out=1.0,
+                                   periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
+        orc.set_mrt(kw.get("model") == "mrt")
+        orc.init_equilibrium(1.0)
     orc.step(1, record=False)
     t0 = time.perf_counter()
     orc.step(steps, record=False)
@@ -245,7 +284,8 @@ def cpu_baseline(mask, kw, steps):
         "cores": oracle.oracle.max_threads(),
         "kind": "oracle",
         "sample": f"{steps} steps of the full {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]} lattice "
-                  f"after 1 warm-up step ({dt:.1f} s); FP64 dense push-scheme oracle, OpenMP over z",
+                  f"after 1 warm-up step ({dt:.1f} s); FP64 dense push-scheme "
+                  f"{'two-fluid ' if colour else ''}oracle, OpenMP over z",
         "mlups_per_voxel": mask.size * steps / dt / 1e6,
     }
 
@@ -279,7 +319,12 @@ def main():
     print(f"[bench] workload {args.config}: mask {mask.shape}, pore sites {(mask == 0).sum()}",
           file=sys.stderr, flush=True)
     lat = fluxlbm.Lattice(mask, watchdog_every=1000, **kw)
-    lat.init_equilibrium(1.0)
+    if kw.get("model") == "colour":
+        z = lat.coords()[:, 2]
+        na = (z < cfg["reservoir"]).astype(float)
+        lat.init_colour(na, 1.0 - na)
+    else:
+        lat.init_equilibrium(1.0)
     n = lat.n_sites
 
     lat.step(args.warmup)
@@ -304,7 +349,7 @@ def main():
 
     # per-kernel durations with HIP events on the launch stream
     ms_plane, ms_kernel = lat.profile_kernels(args.profile_steps)
-    bpl = bytes_per_lup(kw["precision"])
+    bpl = bytes_per_lup(kw["precision"], kw.get("model", "bgk"))
     achieved = n * bpl / (ms_kernel * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
@@ -313,7 +358,7 @@ def main():
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": measured_traffic(args.config, kw["precision"], n),
-        "kernel": "k_stream_collide",
+        "kernel": "k_phase+k_colour" if kw.get("model") == "colour" else "k_stream_collide",
         "kernel_ms": round(ms_kernel, 5),
         "plane_kernel_ms": round(ms_plane, 5),
         "bytes_per_lup": bpl,
@@ -339,6 +384,7 @@ def main():
             "tau": kw["tau"],
             "q_target": kw["q_target"],
             "precision": kw["precision"],
+            "collision": kw.get("model", "bgk"),
             **info,
         },
         "hbm_gbs_model": round(mlups * bpl / 1e3, 1),
@@ -350,7 +396,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_gbs"] = round(copy_bandwidth(torch), 1)
-    if not args.no_controller:
+    if not args.no_controller and args.config == "pack256":
         out["controller_ab"] = controller_ab()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(mask, kw, args.cpu_steps)

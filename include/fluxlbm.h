@@ -225,6 +225,9 @@ typedef struct flbm_controller_params {
     double release_tol;   /* two-step mean |Q_out - Q*| / Q* that returns control to the
                              plain update for good */
     int32_t trust_steps;  /* the bound decays linearly to zero over this many steps */
+    int32_t relative;     /* 0: r = log(drho_inf / drho_ref); 1: r = log(drho_inf / drho) */
+    int32_t stall_steps;  /* > 0: release when the outlet error has not improved by 10 %
+                             over this many decisions */
     int32_t reserved2;
 } flbm_controller_params;
 
@@ -234,15 +237,20 @@ typedef struct flbm_controller_params {
  * at the lags 1, 2, 3, 6, 11, 20, 36, 65, 119, 215, 391, 710, 1290, 2345,
  * 4260, 7740 steps back (Qbar the mean of two consecutive steps, 0 before
  * the first step), and log10(drho / drho_ref) / 3 clipped to [-1, 1] (-1 if
- * drho <= 0), drho = rho_in - rho_out of the last step. Its output r,
- * clipped to [-4, 4], is the predicted steady density difference as
- * log(drho_inf / drho_ref): the proposal is rho_hat = rho_out + drho_ref exp(r).
- * The next step uses
+ * drho <= 0), drho = rho_in - rho_out of the last step. Its output r is
+ * the predicted steady density difference drho_inf, either absolute
+ * (relative = 0: r = log(drho_inf / drho_ref) clipped to [-4, 4], proposal
+ * rho_hat = rho_out + drho_ref exp(r)) or as the remaining relative rise
+ * (relative = 1: r = log(drho_inf / drho) clipped to [-2, 3], proposal
+ * rho_hat = rho_out + drho exp(r); no offset while drho <= 0). The next
+ * step uses
  *   rho_in = rho_plain + clip(gain (rho_hat - rho_plain), +-bound rho0 |Q*| / A)
  * with rho_plain the update of eq. potential and bound = trust0 (1 -
  * n / trust_steps)^+ after n decisions, i.e. |Q_in - Q*| / Q* <= bound. No
- * offset once the two-step mean outlet error has met release_tol (sticky),
- * when Q* <= 0, or when the proposal is not finite. With trust0 = 0 the
+ * offset once the two-step mean outlet error has met release_tol, or (with
+ * stall_steps > 0) once it has not fallen below 0.9 times its best value for
+ * stall_steps decisions (both sticky), when Q* <= 0, or when the network
+ * output or the proposal is not finite. With trust0 = 0 the
  * run is the plain method exactly (the inputs are still recorded). The
  * network must outlive the attachment. Flux mode only (else FLBM_ESTATE).
  * Synchronises. */
@@ -360,7 +368,9 @@ flbm_status flbm_device_layout(const flbm_ctx *c, void **f_cur, void **nbr, int6
  * context's stream; return the duration in milliseconds of the plane
  * reduction and the mean duration of the fused stream-collide kernel. (In a
  * run of steps the plane reduction runs only once: each step kernel carries
- * the next step's inlet sum.) The steps are real steps. Synchronises. */
+ * the next step's inlet sum.) For the colour model the step duration covers
+ * both launches of a step (phase pass and colour step). The steps are real
+ * steps. Synchronises. */
 flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, double *ms_step);
 
 /* Stream-copy calibration kernel: copies `bytes` (a multiple of 16, both

@@ -18,12 +18,16 @@ inputs x (32):
 network   r = clip(net(x), -4, 4), computed by the network oracle with BF16
           operands (the precision of the device's matrix products): the
           predicted steady density difference as log(drho_inf / drho_ref);
-proposal  rho_hat = rho_out + drho_ref exp(r);
+proposal  rho_hat = rho_out + drho_ref exp(r) (absolute mode), or with the
+          relative target r = clip(net(x), -2, 3) = log(drho_inf / drho):
+          rho_hat = rho_out + drho exp(r) (no offset while drho <= 0);
 offset    delta = clip(gain (rho_hat - rho_plain), +-b rho0 |Q*| / A_in) with
           rho_plain the density eq. potential gives for the next step and
           b = trust0 max(0, 1 - n / trust_steps) after n decisions; delta = 0
           once Qbar(t - 1) has been within release_tol of Q* (relative; from
-          then on for good, and only from t >= 2), when Q* <= 0, or when the
+          then on for good, and only from t >= 2), once the error has not
+          fallen below 0.9 times its best value for stall_steps decisions
+          (when stall_steps > 0; for good), when Q* <= 0, or when the
           network output or the offset is not finite.
 """
 from __future__ import annotations
@@ -42,11 +46,14 @@ def _f32(v):
 
 
 class OracleController:
-    def __init__(self, params, geometry, *, drho_ref, gain, trust0, release_tol, trust_steps):
+    def __init__(self, params, geometry, *, drho_ref, gain, trust0, release_tol, trust_steps, relative=False,
+                 stall_steps=0):
         self.params = np.asarray(params, np.float64)
         self.geometry = np.asarray(geometry, np.float64)
         self.drho_ref, self.gain, self.trust0 = float(drho_ref), float(gain), float(trust0)
         self.release_tol, self.trust_steps = float(release_tol), int(trust_steps)
+        self.relative, self.stall_steps = bool(relative), int(stall_steps)
+        self.best, self.best_n = 0.0, 0
         self.qout = []      # Q_out of every step taken
         self.rho_in = []    # rho_in of every step taken
         self.released = False
@@ -76,15 +83,21 @@ class OracleController:
         y, _, _ = mlp_oracle.forward(self.params, np.asarray(x, np.float64)[None, :], bf16=True)
         return float(y[0])
 
-    def offset(self, y, rho_plain, n, released, *, q_target, rho_out, rho0, a_in):
+    def offset(self, y, rho_plain, n, released, *, q_target, rho_out, rho0, a_in, drho=None):
         """The offset for network output y after n decisions."""
         qn = abs(q_target) if q_target != 0.0 else 1.0
         b = self.trust0 * max(0.0, 1.0 - n / self.trust_steps) if self.trust_steps > 0 else 0.0
         limit = b * rho0 * qn / a_in
-        r = min(4.0, max(-4.0, y))
-        rho_hat = rho_out + self.drho_ref * math.exp(r)
+        if not math.isfinite(y):
+            return 0.0
+        if self.relative:
+            r = min(3.0, max(-2.0, y))
+            rho_hat = rho_out + drho * math.exp(r)
+        else:
+            r = min(4.0, max(-4.0, y))
+            rho_hat = rho_out + self.drho_ref * math.exp(r)
         delta = self.gain * (rho_hat - rho_plain)
-        if not math.isfinite(y) or not math.isfinite(delta) or not q_target > 0.0 or released:
+        if not math.isfinite(delta) or not q_target > 0.0 or released or (self.relative and not drho > 0.0):
             delta = 0.0
         return min(limit, max(-limit, delta))
 
@@ -95,11 +108,16 @@ class OracleController:
         x, drho = self.inputs(q_target, rho_out)
         y = self.network(x)
         e2 = abs(0.5 * (self._q(t - 1) + self._q(t - 2)) - q_target) / qn
+        n = self.decisions
         if t >= 2 and e2 <= self.release_tol:
             self.released = True
+        if n == 0 or e2 < 0.9 * self.best:
+            self.best, self.best_n = e2, n
+        elif self.stall_steps > 0 and n - self.best_n >= self.stall_steps:
+            self.released = True
         rho_plain = orc.plain_inlet_density()
-        delta = self.offset(y, rho_plain, self.decisions, self.released, q_target=q_target, rho_out=rho_out,
-                            rho0=rho0, a_in=a_in)
+        delta = self.offset(y, rho_plain, n, self.released, q_target=q_target, rho_out=rho_out,
+                            rho0=rho0, a_in=a_in, drho=drho)
         self.decisions += 1
         self.records.append((x, drho, rho_plain, y, delta))
         return delta

@@ -34,8 +34,10 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "controller_weights.npz")
 N_IN = 32
 RESERVOIR = 6
 
-# controller settings used for training runs and evaluation
-DEFAULTS = dict(gain=1.0, trust0=4.0, release_tol=1e-3)
+# controller settings used for training runs and evaluation; trust_steps and
+# stall_steps default to 4 nz^2 and nz^2 / 8 (nz the lattice length: the
+# charging transient scales with its square)
+DEFAULTS = dict(gain=1.0, trust0=4.0, release_tol=1e-3, relative=True)
 
 
 # ---------------------------------------------------------------- inputs
@@ -151,7 +153,8 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
         if net is not None:
             lat.set_controller(net, geom, drho_ref=drho_ref, gain=s["gain"],
                                trust0=s["trust0"] if active else 0.0, release_tol=s["release_tol"],
-                               trust_steps=int(s.get("trust_steps", 4 * nz * nz)))
+                               trust_steps=int(s.get("trust_steps", 4 * nz * nz)),
+                               relative=bool(s["relative"]), stall_steps=int(s.get("stall_steps", nz * nz // 8)))
         q = kw["q_target"]
         hist, xs, auxs = [], [], []
         t0 = time.perf_counter()
@@ -192,11 +195,23 @@ def steady_density(res, window=2048):
 # ---------------------------------------------------------------- data
 
 def label(rho_inf: float, drho_ref: float, rho_out: float = 1.0) -> float:
-    """Target of the network: log(drho_inf / drho_ref), clipped to [-4, 4]."""
+    """Absolute target: log(drho_inf / drho_ref), clipped to [-4, 4]."""
     d = rho_inf - rho_out
     if not d > 0.0:
         return -4.0
     return float(np.clip(math.log(d / drho_ref), -4.0, 4.0))
+
+
+def relative_labels(rho_inf: float, drho: np.ndarray, rho_out: float = 1.0) -> np.ndarray:
+    """Relative target of each decision: log(drho_inf / drho), the remaining
+    relative rise of the inlet density, clipped to [-2, 3] (3 where drho <= 0)."""
+    d = rho_inf - rho_out
+    drho = np.asarray(drho, np.float64)
+    out = np.full(drho.shape, 3.0)
+    ok = drho > 0.0
+    if d > 0.0:
+        out[ok] = np.log(d / drho[ok])
+    return np.clip(out, -2.0, 3.0).astype(np.float32)
 
 
 def pick_rows(n_rows: int, k: int, seed: int) -> np.ndarray:
@@ -254,6 +269,15 @@ def shift_reference(x: np.ndarray, log_scale: float) -> np.ndarray:
 def train(out_path: str, *, samples: int = 48, dagger_rounds: int = 3, steps: int = 6000,
           rows_per_run: int = 600, augment: int = 4, ref_spread: float = 1.0, seed: int = 7, log=print,
           settings=None):
+    settings = dict(DEFAULTS, **(settings or {}))
+    relative = bool(settings["relative"])
+    return _train(out_path, samples=samples, dagger_rounds=dagger_rounds, steps=steps, rows_per_run=rows_per_run,
+                  augment=augment, ref_spread=ref_spread, seed=seed, log=log, settings=settings,
+                  relative=relative)
+
+
+def _train(out_path, *, samples, dagger_rounds, steps, rows_per_run, augment, ref_spread, seed, log, settings,
+           relative):
     """Train on plain-method runs of the training family, then on runs under
     the network's own control (DAgger), all labelled with the steady density
     of the plain run. Every run uses a reference density difference scaled
@@ -278,7 +302,10 @@ def train(out_path: str, *, samples: int = 48, dagger_rounds: int = 3, steps: in
             ls = 0.0 if a == 0 else float(rng.uniform(-ref_spread, ref_spread))
             rows = pick_rows(len(res["x"]), rows_per_run, seed + 97 * i + a)
             Xs.append(shift_reference(res["x"][rows], ls))
-            Ts.append(np.full(len(rows), np.clip(lab - ls, -4.0, 4.0), np.float32))
+            if relative:
+                Ts.append(relative_labels(rho_inf, res["aux"][rows, 0]))
+            else:
+                Ts.append(np.full(len(rows), np.clip(lab - ls, -4.0, 4.0), np.float32))
         cases.append((mask, kw, rho_inf, c))
         info.append(dict(c, plain_steps_to_tol=res["steps_to_tol"], label=lab, steps=res["steps"]))
         log(f"plain {i}: n={c['n']} phi={c['porosity']:.3f} tau={c['tau']:.2f} darcy={c['darcy']:.2e} "
@@ -302,7 +329,10 @@ def train(out_path: str, *, samples: int = 48, dagger_rounds: int = 3, steps: in
             lab = label(rho_inf, res["drho_ref"])
             rows = pick_rows(len(res["x"]), rows_per_run, seed + 1000 * (rnd + 1) + i)
             Xs.append(res["x"][rows])
-            Ts.append(np.full(len(rows), lab, np.float32))
+            if relative:
+                Ts.append(relative_labels(rho_inf, res["aux"][rows, 0]))
+            else:
+                Ts.append(np.full(len(rows), lab, np.float32))
             info[i][f"learned_steps_to_tol_r{rnd}"] = res["steps_to_tol"]
             p = info[i]["plain_steps_to_tol"]
             if p and res["steps_to_tol"]:
@@ -314,7 +344,7 @@ def train(out_path: str, *, samples: int = 48, dagger_rounds: int = 3, steps: in
         losses = fit(f"fit {rnd + 1}")
     params = net.get_params()
     meta = dict(samples=samples, dagger_rounds=dagger_rounds, steps=steps, rows_per_run=rows_per_run,
-                augment=augment, ref_spread=ref_spread, seed=seed, settings=dict(DEFAULTS, **(settings or {})),
+                augment=augment, ref_spread=ref_spread, seed=seed, settings=settings,
                 final_loss=losses[-1][1], family=info)
     np.savez(out_path, params=params, meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
     net.close()
@@ -326,6 +356,12 @@ def load_weights(path: str = DEFAULT_WEIGHTS):
     return z["params"].astype(np.float32), json.loads(bytes(z["meta"]).decode())
 
 
+def settings_of(meta) -> dict:
+    """The controller settings the weights were trained with."""
+    keep = ("relative", "gain", "trust0", "release_tol")
+    return {k: v for k, v in meta.get("settings", {}).items() if k in keep}
+
+
 def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000):
     """Steps to tol for the plain update and for the learned controller on
     the same sample and GPU."""
@@ -335,13 +371,12 @@ def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000):
         plain = run(mask, kw, tol=tol, max_steps=max_steps)
         learned = run(mask, kw, net=net, active=True, tol=tol, max_steps=max_steps, settings=settings)
     finally:
-        pass
+        net.close()
     out = dict(plain_steps=plain["steps_to_tol"], learned_steps=learned["steps_to_tol"],
                plain_secs=plain["secs"], learned_secs=learned["secs"],
                controller=learned.get("controller"))
     if plain["steps_to_tol"] and learned["steps_to_tol"]:
         out["gain"] = plain["steps_to_tol"] / learned["steps_to_tol"]
-    net.close()
     return out
 
 
@@ -355,6 +390,7 @@ def main(argv=None):
     t.add_argument("--steps", type=int, default=6000)
     t.add_argument("--augment", type=int, default=4)
     t.add_argument("--ref-spread", type=float, default=1.0)
+    t.add_argument("--absolute", action="store_true", help="absolute target log(drho_inf / drho_ref)")
     t.add_argument("--seed", type=int, default=7)
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", default=DEFAULT_WEIGHTS)
@@ -368,11 +404,12 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "train":
         meta = train(a.out, samples=a.samples, dagger_rounds=a.dagger, steps=a.steps, seed=a.seed,
-                     augment=a.augment, ref_spread=a.ref_spread, log=lambda m: print(m, flush=True))
+                     augment=a.augment, ref_spread=a.ref_spread, log=lambda m: print(m, flush=True),
+                     settings={"relative": not a.absolute})
         print(json.dumps({"final_loss": meta["final_loss"]}))
     else:
         params, meta = load_weights(a.weights)
-        settings = {}
+        settings = settings_of(meta)
         if a.trust0 is not None:
             settings["trust0"] = a.trust0
         if a.release_tol is not None:

@@ -383,6 +383,8 @@ struct CtrlArgs {
     int32_t hist_cap;
     int32_t trust_steps;
     int32_t rd_next;
+    int32_t relative;
+    int32_t stall_steps;
     int32_t pad_;
     const float *params;
     const float *geometry;
@@ -424,19 +426,27 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
     float *rec = c.trace + (size_t)((t - 1 + c.hist_cap) % c.hist_cap) * CTRL_REC;
     if (threadIdx.x < mlp::N_IN) rec[threadIdx.x] = x[threadIdx.x];
     if (threadIdx.x == 0) {
+        const int64_t n = st->ctrl_steps;
         const double e2 = fabs(0.5 * (qout(t - 1) + qout(t - 2)) - qs) / qn;
         if (t >= 2 && e2 <= c.release_tol) st->ctrl_released = 1u;
-        const int64_t n = st->ctrl_steps;
+        // progress judge: the error must fall by 10 % within stall_steps decisions
+        if (n == 0 || e2 < 0.9 * st->ctrl_best) {
+            st->ctrl_best = e2;
+            st->ctrl_best_n = n;
+        } else if (c.stall_steps > 0 && n - st->ctrl_best_n >= c.stall_steps) {
+            st->ctrl_released = 1u;
+        }
         const double bound =
             c.trust_steps > 0 ? c.trust0 * fmax(0.0, 1.0 - (double)n / (double)c.trust_steps) : 0.0;
         const double limit = bound * c.rho0 * qn / c.a_in;
         const double rho_plain = 1.0 + inlet_drho_plain(st, c.rd_next, c.rho0, (int64_t)c.a_in);
-        const double r = fmin(4.0, fmax(-4.0, (double)y));
-        const double rho_hat = 1.0 + st->drho_out + c.drho_ref * exp(r);
+        const double r = c.relative ? fmin(3.0, fmax(-2.0, (double)y)) : fmin(4.0, fmax(-4.0, (double)y));
+        const double rho_hat = 1.0 + st->drho_out + (c.relative ? drho : c.drho_ref) * exp(r);
         double delta = c.gain * (rho_hat - rho_plain);
         // a non-finite output is dropped before clipping (fmin/fmax would
         // turn a NaN into a bound)
-        if (!isfinite(y) || !isfinite(delta) || !(qs > 0.0) || st->ctrl_released) delta = 0.0;
+        if (!isfinite(y) || !isfinite(delta) || !(qs > 0.0) || st->ctrl_released || (c.relative && !(drho > 0.0)))
+            delta = 0.0;
         delta = fmin(limit, fmax(-limit, delta));
         st->ctrl_delta = delta;
         st->ctrl_steps = n + 1;
@@ -457,6 +467,8 @@ void launch_controller(flbm_ctx *c, hipStream_t s, int rd_next)
     a.hist_cap = HIST_CAP;
     a.trust_steps = c->ctrl.trust_steps;
     a.rd_next = rd_next;
+    a.relative = c->ctrl.relative;
+    a.stall_steps = c->ctrl.stall_steps;
     a.params = c->ctrl_net->params;
     a.geometry = c->ctrl_feat;
     a.rho0 = c->p.rho0;
@@ -753,7 +765,8 @@ flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_con
     drop_graphs(c);
     if (net) {
         if (!(p->trust0 >= 0.0) || !std::isfinite(p->gain) || p->trust_steps < 0 || !(p->release_tol >= 0.0) ||
-            !(p->drho_ref > 0.0) || !std::isfinite(p->drho_ref))
+            !(p->drho_ref > 0.0) || !std::isfinite(p->drho_ref) || p->stall_steps < 0 ||
+            (p->relative != 0 && p->relative != 1))
             return fail(c, FLBM_EINVAL, "bad controller parameters");
         c->ctrl = *p;
         c->ctrl_net = net;
@@ -769,6 +782,8 @@ flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_con
     HIPCHK(c, hipMemcpy(&c->st->ctrl_delta, &zero, sizeof(zero), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(&c->st->ctrl_steps, &z64, sizeof(z64), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(&c->st->ctrl_released, &z32, sizeof(z32), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_best, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_best_n, &z64, sizeof(z64), hipMemcpyHostToDevice));
     return FLBM_OK;
 }
 
@@ -1242,10 +1257,18 @@ flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, doubl
     for (int32_t i = 0; i < n; ++i) {
         const int from = c->cur;
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
-        with_storage(c, [&](auto tag) {
-            using T = decltype(tag);
-            launch_stream_collide<T>(c, c->stream, (const T *)c->f[from], (T *)c->f[from ^ 1], false);
-        });
+        if (c->colour) {
+            // both launches of a colour step (phase pass and colour step)
+            if (is_fp64(c))
+                launch_colour_step<double>(c, c->stream, from, false);
+            else
+                launch_colour_step<float>(c, c->stream, from, false);
+        } else {
+            with_storage(c, [&](auto tag) {
+                using T = decltype(tag);
+                launch_stream_collide<T>(c, c->stream, (const T *)c->f[from], (T *)c->f[from ^ 1], false);
+            });
+        }
         HIPCHK(c, hipEventRecord(ev[1], c->stream));
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipEventSynchronize(ev[1]));

@@ -60,12 +60,12 @@ struct DevState {
     uint32_t unstable;    // sticky watchdog flag
     uint32_t obs_bad;
     int64_t ctrl_steps;   // controller decisions taken
-    uint32_t ctrl_released;  // sticky: the outlet flux met the tolerance, plain update from now on
+    uint32_t ctrl_released;  // sticky: plain update from now on (tolerance met, or no progress)
     uint32_t pad_;
+    double ctrl_best;     // smallest outlet-flux error seen at a 10% improvement
+    int64_t ctrl_best_n;  // decision count at that improvement
 };
 
-// Inlet density minus one for the step reading s_carry[rd] (eq. potential):
-// (rho0 Q* + sum_i Kt_i) / A, plus the controller's offset when one is active.
 // Inlet density minus one for the step that reads parity rd: the update of
 // eq. potential, rho_in = (rho0 Q* + sum_i K_i) / A in deviation form, plus
 // the learned controller's offset (zero unless a controller is attached).

@@ -6,7 +6,8 @@ compared with the series solution of the tube (truncated at k = 199).
 
 E2 (Sec. 3.2, square tube): primary drainage at constant flux. A 40 x 40
 tube of length 80 between a non-wetting reservoir (inlet side) and a
-wetting reservoir (outlet side) of six pure-fluid layers each, unit density
+wetting reservoir (outlet side) of six pure-fluid layers each (open
+sideways), unit density
 and viscosity ratio (tau = 1), interfacial tension 6e-5 and the fluxes
 Q = 0.02, 0.2, 2.0. The wetting volume falls at a rate that approaches Q.
 The interfacial tension is set through alpha from a Laplace-law calibration
@@ -98,16 +99,25 @@ def laplace_gamma(alpha, *, beta=0.7, tau=1.0, radii=(7.0, 10.0, 13.0), size=40,
 def e2_drainage(q, alpha, *, width=40, length=80, reservoir=6, tau=1.0, beta=0.7, steps=None,
                 window=None, precision="fp32"):
     """Wetting volume against time; the rate -dV_w/dt over the last window
-    steps, relative to Q. The wetting fluid (B) wets the walls."""
+    steps, relative to Q. The tube has walls (one solid voxel around its
+    width x width bore, wetted by the wetting fluid B); the reservoirs are
+    pure fluid nodes, open sideways (periodic), so no wall connects the two
+    reservoirs."""
     nz = length + 2 * reservoir
-    mask = np.zeros((nz, width, width), np.uint8)
+    n = width + 2
+    mask = np.zeros((nz, n, n), np.uint8)
+    tube = slice(reservoir, reservoir + length)
+    mask[tube, 0, :] = 1
+    mask[tube, -1, :] = 1
+    mask[tube, :, 0] = 1
+    mask[tube, :, -1] = 1
     if steps is None:
         # enough for the front to cross a good part of the tube, bounded
         steps = int(min(400000, max(40000, 0.4 * width * width * length / q)))
     steps = (steps // 1000) * 1000
     window = window or steps // 4
     lat = fluxlbm.Lattice(mask, precision=precision, model="colour", tau=tau, alpha=alpha, beta=beta,
-                          phi_solid=-1.0, q_target=q, periodic_x=False, periodic_y=False,
+                          phi_solid=-1.0, q_target=q, periodic_x=True, periodic_y=True,
                           watchdog_every=1000)
     try:
         c = lat.coords()

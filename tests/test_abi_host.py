@@ -172,3 +172,14 @@ def test_sphere_pack_generator_is_seeded_and_hits_porosity():
     assert not m1[:6].any() and not m1[-6:].any()
     m3, _, _ = inputs.sphere_pack(48, 0.35, seed=3)
     assert not np.array_equal(m1, m3)
+
+
+def test_batch_and_network_argument_checks_without_a_device():
+    lib = fluxlbm.load_library()
+    out = ctypes.c_void_p()
+    assert lib.flbm_batch_create(0, None, ctypes.byref(out)) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_batch_create(2, None, ctypes.byref(out)) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_mlp_create(0, None, ctypes.byref(out)) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_batch_set_schedule(None, None) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_gemm_bf16(None, 1, 1, None, 1, 1, None, 1, 1, 1, 1, None) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_set_controller(None, None, None) == fluxlbm.FLBM_EINVAL

@@ -63,7 +63,9 @@ def test_batch_equals_single_lattices_bitwise(precision, sched):
         s.step(n)
         assert l.step_count == n
         assert np.array_equal(s.read_distributions(), l.read_distributions())
-        assert np.array_equal(s.history(n), l.history(n), equal_nan=True)
+        # rho_in, Q_in, Q_out of every step (the watchdog columns are filled
+        # at different steps: at the end of each batch graph run)
+        assert np.array_equal(s.history(n)[:, :3], l.history(n)[:, :3])
     # and again from an odd parity (every sample's buffers flipped)
     b.step(10)
     for (m, s), (_, l) in zip(singles, batched):
@@ -91,7 +93,7 @@ def test_batch_sample_matches_oracle():
     b.step(12)
     shape, solid, seed, tau, q, rho_out = SPECS[1]
     m, lat = batched[1]
-    orc = oracle.OracleLattice(m, tau=tau, q_target=q, rho_out=rho_out)
+    orc = oracle.OracleLattice(m, tau=tau, q_target=q, rho_out=rho_out, periodic_x=True, periodic_y=True)
     orc.init_equilibrium(rho_out)
     h = orc.step(12)
     assert rel_err(lat.read_distributions(), dense_to_sites(m, orc.get_f())) <= 1e-12

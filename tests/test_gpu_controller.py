@@ -35,7 +35,7 @@ def _params(seed, b3, scale=0.3):
 GEOM = np.linspace(-0.5, 0.5, 15).astype(np.float32)
 
 
-def _run_pair(gain, trust0, b3, n=80):
+def _run_pair(gain, trust0, b3, n=80, relative=False, stall_steps=0):
     mask = _mask()
     q = 0.02
     lat, orc = pair(mask, precision="fp64", tau=0.9, q_target=q)
@@ -44,7 +44,8 @@ def _run_pair(gain, trust0, b3, n=80):
     params = _params(81, b3)
     net = fluxlbm.Mlp(16)
     net.set_params(params)
-    kw = dict(drho_ref=1e-3, gain=gain, trust0=trust0, release_tol=1e-12, trust_steps=50)
+    kw = dict(drho_ref=1e-3, gain=gain, trust0=trust0, release_tol=1e-12, trust_steps=50, relative=relative,
+              stall_steps=stall_steps)
     lat.set_controller(net, GEOM, **kw)
     oc = OracleController(params.astype(np.float64), GEOM, **kw)
     lat.step(n)
@@ -54,11 +55,12 @@ def _run_pair(gain, trust0, b3, n=80):
     return lat, orc, net, oc, hg, ho, x, aux, q, kw
 
 
-def test_clipped_decisions_match_oracle_exactly():
+@pytest.mark.parametrize("relative", [False, True])
+def test_clipped_decisions_match_oracle_exactly(relative):
     # every proposal lies far above the trust bound, so each offset is the
     # bound itself: the same FP64 number on both sides, and the two runs stay
     # equal to rounding
-    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(1.0, 0.5, 8.0)
+    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(1.0, 0.5, 8.0, relative=relative)
     xo = np.array([r[0] for r in oc.records])
     auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
     assert np.max(np.abs(x - xo)) <= 1e-6
@@ -77,12 +79,13 @@ def test_clipped_decisions_match_oracle_exactly():
     net.close()
 
 
-def test_proportional_decisions_follow_the_rule():
+@pytest.mark.parametrize("relative", [False, True])
+def test_proportional_decisions_follow_the_rule(relative):
     # offsets inside the bound carry the network's FP32 output: check each
     # device decision against the rule evaluated by the oracle on the
     # device's own record, then the trajectory against the oracle run with
     # the propagated tolerance
-    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(0.2, 50.0, -0.3)
+    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(0.2, 50.0, -0.3, relative=relative)
     a_in = orc.a_in
     for k in range(80):
         # inputs from the device's own history of Q_out and rho_in
@@ -94,12 +97,13 @@ def test_proportional_decisions_follow_the_rule():
         assert abs(aux[k, 0] - drho) <= 1e-15
         y = ref.network(x[k].astype(np.float64))
         assert abs(aux[k, 2] - y) <= 2e-4 * max(1.0, abs(y)), k
-        d = ref.offset(aux[k, 2], aux[k, 1], k, False, q_target=q, rho_out=1.0, rho0=1.0, a_in=a_in)
+        d = ref.offset(aux[k, 2], aux[k, 1], k, False, q_target=q, rho_out=1.0, rho0=1.0, a_in=a_in,
+                       drho=aux[k, 0])
         assert abs(aux[k, 3] - d) <= 1e-15 + 1e-12 * abs(d), k
     assert np.any(np.abs(aux[:50, 3]) > 0) and np.all(aux[50:, 3] == 0.0)
     auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
-    scale = kw["drho_ref"] * math.exp(4.0) * kw["gain"]
-    assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 2e-4 * scale
+    scale = (np.abs(aux[:, 0]).max() * math.exp(3.0) if relative else kw["drho_ref"] * math.exp(4.0)) * kw["gain"]
+    assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 2e-4 * scale + 1e-12
     assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 2e-4 * scale + 1e-12
     lat.close()
     net.close()
@@ -177,6 +181,24 @@ def test_release_returns_control_for_good():
     net.close()
 
 
+def test_no_progress_returns_control():
+    # a constant network holds the inlet at a fixed density; once the outlet
+    # error stops falling by 10 % within stall_steps decisions, the plain
+    # update takes over for good
+    p = np.zeros(mo.N_PARAMS, np.float32)
+    p[-1] = 0.5
+    (fa, fb, ha, hb, b), net = _plain_and_controlled(
+        p, dict(drho_ref=2e-3, trust0=5.0, release_tol=1e-12, trust_steps=10 ** 6, stall_steps=40), steps=1500)
+    _, released, delta, decisions = b.controller_state()
+    assert released and delta == 0.0
+    _, aux = b.controller_trace(1500)
+    first_zero = int(np.argmax(aux[:, 3] == 0.0))
+    assert first_zero > 40 and np.all(aux[first_zero:, 3] == 0.0)
+    assert np.allclose(hb[first_zero + 1:, 1], 0.02, rtol=1e-9)   # plain: the inlet flux is exact
+    b.close()
+    net.close()
+
+
 def test_controller_rejected_without_flux_inlet():
     mask = _mask()
     lat = fluxlbm.Lattice(mask, precision="fp32", z_mode=fluxlbm.FLBM_Z_PERIODIC)
@@ -190,9 +212,17 @@ def test_controller_rejected_without_flux_inlet():
 
 @pytest.mark.skipif(not os.path.exists(controller.DEFAULT_WEIGHTS), reason="no trained controller weights")
 def test_trained_controller_reaches_tolerance_sooner():
-    # a held-out sample of the training family's kind (seed outside it)
-    params, _ = controller.load_weights()
-    mask, kw = controller.make_sample(64, 0.3, 4242, tau=0.8, darcy=1e-5)
-    r = controller.evaluate(params, mask, kw, max_steps=200000)
-    assert r["plain_steps"] is not None and r["learned_steps"] is not None
-    assert r["learned_steps"] < r["plain_steps"], r
+    """What the trained network gains: on held-out packs (seeds outside the
+    training family) the learned controller reaches |Q_out - Q*| / Q* <= 1e-3
+    for good in fewer steps than the plain update, in total over the set."""
+    params, meta = controller.load_weights()
+    settings = controller.settings_of(meta)
+    plain = learned = 0
+    for seed in (4242, 4243, 4244):
+        mask, kw = controller.make_sample(64, 0.3, seed, tau=0.8, darcy=1e-5)
+        r = controller.evaluate(params, mask, kw, max_steps=200000, settings=settings)
+        assert r["plain_steps"] is not None and r["learned_steps"] is not None, r
+        plain += r["plain_steps"]
+        learned += r["learned_steps"]
+    print(f"steps to 1e-3: plain {plain}, learned {learned}, gain {plain / learned:.2f}")
+    assert learned < plain
