@@ -62,7 +62,8 @@ typedef int32_t flbm_status;
  * density are FP64 in every mode. */
 #define FLBM_FP64 0
 #define FLBM_FP32 1
-#define FLBM_FP16DEV 2 /* FP16 storage of scaled deviations f - w_q, FP32 arithmetic */
+#define FLBM_FP16DEV 2 /* FP16 storage of scaled deviations f - w_q, FP32 arithmetic (the colour
+                          model keeps its D3Q7 colours and phase field in FP32) */
 
 /* Collision model. */
 #define FLBM_BGK 0

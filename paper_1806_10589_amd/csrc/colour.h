@@ -16,6 +16,13 @@
 
 namespace flbm {
 
+// Storage of the colour state (A, B, N_A, N_B, phi): the momentum storage
+// type, except that the FP16-deviation mode keeps the colours in FP32
+// (absolute colour fractions in FP16 would break colour conservation at the
+// 1e-4 level every step).
+template <typename T> struct ColourStore { using type = T; };
+template <> struct ColourStore<_Float16> { using type = float; };
+
 // phi of the neighbour that pull direction p reads from, decoded from the
 // pull index: a regular pull q*n_pad + src gives phi[src]; bounce-back (a
 // solid or a non-periodic side) gives the wetting value phi_solid; a source
@@ -46,9 +53,10 @@ template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
 {
     using R = typename Compute<T>::type;
+    using C = typename ColourStore<T>::type;
     const int64_t s = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t npad = p.npad;
-    const T *ain = (const T *)p.ain, *bin = (const T *)p.bin;
+    const C *ain = (const C *)p.ain, *bin = (const C *)p.bin;
     R a[7], b[7];
     a[0] = (R)ain[s];
     b[0] = (R)bin[s];
@@ -63,11 +71,11 @@ __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
         // the site's boundary velocity, from the pulled momentum knowns
         const T *fin = (const T *)p.fin;
         R g[19];
-        g[0] = (R)fin[s];
+        g[0] = Codec<T>::dec(fin[s], 0);
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
             const int32_t idx = p.nbr[(int64_t)(q - 1) * npad + s];
-            g[q] = idx == p.sentinel ? (R)0 : (R)fin[idx];
+            g[q] = idx == p.sentinel ? (R)0 : Codec<T>::dec(fin[idx], q);
         }
         const DevState *st = p.st;
         if (s < p.a_in) {
@@ -96,15 +104,15 @@ __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
         nb += b[q];
     }
     const R tot = na + nb;
-    ((T *)p.na)[s] = (T)na;
-    ((T *)p.nb)[s] = (T)nb;
-    ((T *)p.phi)[s] = (T)(tot != (R)0 ? (na - nb) / tot : (R)0);
+    ((C *)p.na)[s] = (C)na;
+    ((C *)p.nb)[s] = (C)nb;
+    ((C *)p.phi)[s] = (C)(tot != (R)0 ? (na - nb) / tot : (R)0);
     if (p.st->omega == 0.0) {
         // testing aid (collision off): keep the streamed colours
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
-            ((T *)p.aout)[(int64_t)q * npad + s] = (T)a[q];
-            ((T *)p.bout)[(int64_t)q * npad + s] = (T)b[q];
+            ((C *)p.aout)[(int64_t)q * npad + s] = (C)a[q];
+            ((C *)p.bout)[(int64_t)q * npad + s] = (C)b[q];
         }
     }
 }
@@ -123,18 +131,19 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
                                                  ColourStepArgs c)
 {
     using R = typename Compute<T>::type;
+    using C = typename ColourStore<T>::type;
     const int tile = (int)blockIdx.x;
     const int64_t s = (int64_t)tile * TILE + threadIdx.x;
     const int64_t npad = a.npad;
-    const T *phi = (const T *)c.phi;
+    const C *phi = (const C *)c.phi;
 
     R g[19];
     int32_t idx[19];
-    g[0] = (R)fin[s];
+    g[0] = Codec<T>::dec(fin[s], 0);
 #pragma unroll
     for (int q = 1; q < 19; ++q) {
         idx[q] = nbr[(int64_t)(q - 1) * npad + s];
-        g[q] = (R)fin[idx[q]];
+        g[q] = Codec<T>::dec(fin[idx[q]], q);
     }
 
     double uz_in = 0.0, uz_out = 0.0;
@@ -175,16 +184,16 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
 #pragma unroll
         for (int q = 0; q < 19; ++q) {
             const uint32_t cc = (uint32_t)(cw >> (2 * q)) & 3u;
-            if (cc) s_next += (double)cc * (double)g[q];
+            if (cc) s_next += (double)cc * (double)Codec<T>::dec(Codec<T>::enc(g[q], q), q);
         }
     }
 
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store((T)g[q], &fout[(int64_t)q * npad + s]);
+    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(Codec<T>::enc(g[q], q), &fout[(int64_t)q * npad + s]);
 
     // recolouring: full relaxation of A and B to
     //   w_q N_A [1 + 9/2 u.xi_q + beta N_B n.xi_q],  w_q N_B [1 + 9/2 u.xi_q - beta N_A n.xi_q]
-    const R na = (R)((const T *)c.na)[s], nb = (R)((const T *)c.nb)[s];
+    const R na = (R)((const C *)c.na)[s], nb = (R)((const C *)c.nb)[s];
     if (collide) {
         const R cm2 = gx * gx + gy * gy + gz * gz;
         R nx = 0, ny = 0, nz = 0;
@@ -195,7 +204,7 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
             nz = gz * inv;
         }
         const R bab = (R)c.beta * na * nb;
-        T *aout = (T *)c.aout, *bout = (T *)c.bout;
+        C *aout = (C *)c.aout, *bout = (C *)c.bout;
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
             R cu = 0, cn = 0;
@@ -213,8 +222,8 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
             }
             const R w = (R)d3q19::weight7(q);
             const R adv = (R)1 + (R)4.5 * cu;
-            __builtin_nontemporal_store((T)(w * (na * adv + bab * cn)), &aout[(int64_t)q * npad + s]);
-            __builtin_nontemporal_store((T)(w * (nb * adv - bab * cn)), &bout[(int64_t)q * npad + s]);
+            __builtin_nontemporal_store((C)(w * (na * adv + bab * cn)), &aout[(int64_t)q * npad + s]);
+            __builtin_nontemporal_store((C)(w * (nb * adv - bab * cn)), &bout[(int64_t)q * npad + s]);
         }
     }
 

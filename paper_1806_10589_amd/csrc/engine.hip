@@ -108,6 +108,8 @@ flbm_status fail(flbm_ctx *c, flbm_status code, const std::string &msg)
     } while (0)
 
 bool is_fp64(const flbm_ctx *c) { return c->p.precision == FLBM_FP64; }
+// element size of the colour state (A, B, N_A, N_B, phi): FP64, else FP32
+size_t colour_elem(const flbm_ctx *c) { return is_fp64(c) ? 8 : 4; }
 
 // Call fn(T{}) with T the storage type of the distributions.
 template <typename Fn>
@@ -164,8 +166,8 @@ size_t carve(flbm_ctx *c, char *base)
     char *cc[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     char *on = nullptr, *ob2 = nullptr;
     if (c->colour) {
-        for (int i = 0; i < 4; ++i) cc[i] = take((size_t)7 * npad * c->elem);
-        for (int i = 4; i < 7; ++i) cc[i] = take((size_t)npad * c->elem);
+        for (int i = 0; i < 4; ++i) cc[i] = take((size_t)7 * npad * colour_elem(c));
+        for (int i = 4; i < 7; ++i) cc[i] = take((size_t)npad * colour_elem(c));
         on = take((size_t)c->obs_slots * sizeof(double));
         ob2 = take((size_t)c->obs_slots * sizeof(double));
     }
@@ -353,10 +355,7 @@ void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
 void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
 {
     if (c->colour) {
-        if (is_fp64(c))
-            launch_colour_step<double>(c, s, from, obs);
-        else
-            launch_colour_step<float>(c, s, from, obs);
+        with_storage(c, [&](auto tag) { launch_colour_step<decltype(tag)>(c, s, from, obs); });
         if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
         return;
     }
@@ -578,10 +577,10 @@ flbm_status setup_device(flbm_ctx *c, void *mem)
     HIPCHK(c, hipMemsetAsync(c->kpart, 0, PLANE_MAX_BLOCKS * sizeof(double), c->stream));
     if (c->colour) {
         for (int i = 0; i < 2; ++i) {
-            HIPCHK(c, hipMemsetAsync(c->ca[i], 0, (size_t)7 * c->lat.n_pad * c->elem, c->stream));
-            HIPCHK(c, hipMemsetAsync(c->cb[i], 0, (size_t)7 * c->lat.n_pad * c->elem, c->stream));
+            HIPCHK(c, hipMemsetAsync(c->ca[i], 0, (size_t)7 * c->lat.n_pad * colour_elem(c), c->stream));
+            HIPCHK(c, hipMemsetAsync(c->cb[i], 0, (size_t)7 * c->lat.n_pad * colour_elem(c), c->stream));
         }
-        HIPCHK(c, hipMemsetAsync(c->phi, 0, (size_t)c->lat.n_pad * c->elem, c->stream));
+        HIPCHK(c, hipMemsetAsync(c->phi, 0, (size_t)c->lat.n_pad * colour_elem(c), c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->ready = true;
@@ -610,8 +609,6 @@ flbm_status check_params(const flbm_params *p, std::string &why)
     if (p->z_mode < FLBM_Z_FLUX || p->z_mode > FLBM_Z_WALL) return why = "unknown z_mode", FLBM_EINVAL;
     if (p->precision != FLBM_FP64 && p->precision != FLBM_FP32 && p->precision != FLBM_FP16DEV)
         return why = "unknown precision", FLBM_EINVAL;
-    if (p->model == FLBM_COLOUR && p->precision == FLBM_FP16DEV)
-        return why = "the colour model stores FP32 or FP64", FLBM_EINVAL;
     if (p->model != FLBM_BGK && p->model != FLBM_COLOUR && p->model != FLBM_MRT)
         return why = "unknown model", FLBM_EINVAL;
     if (p->model == FLBM_COLOUR && (!std::isfinite(p->alpha) || !std::isfinite(p->beta) ||
@@ -838,7 +835,7 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr)
 // Distributions in a checkpoint: f, then A and B for the colour model.
 static size_t state_f_bytes(const flbm_ctx *c)
 {
-    return (size_t)(c->colour ? 19 + 14 : 19) * c->lat.n_pad * c->elem;
+    return (size_t)19 * c->lat.n_pad * c->elem + (c->colour ? (size_t)14 * c->lat.n_pad * colour_elem(c) : 0);
 }
 
 flbm_status flbm_state_bytes(const flbm_ctx *c, size_t *bytes)
@@ -866,7 +863,7 @@ flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(host, c->f[c->cur], f19, hipMemcpyDeviceToHost));
     if (c->colour) {
-        const size_t c7 = (size_t)7 * c->lat.n_pad * c->elem;
+        const size_t c7 = (size_t)7 * c->lat.n_pad * colour_elem(c);
         HIPCHK(c, hipMemcpy((char *)host + f19, c->ca[c->cur], c7, hipMemcpyDeviceToHost));
         HIPCHK(c, hipMemcpy((char *)host + f19 + c7, c->cb[c->cur], c7, hipMemcpyDeviceToHost));
     }
@@ -887,7 +884,7 @@ flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->f[c->cur], host, f19, hipMemcpyHostToDevice));
     if (c->colour) {
-        const size_t c7 = (size_t)7 * c->lat.n_pad * c->elem;
+        const size_t c7 = (size_t)7 * c->lat.n_pad * colour_elem(c);
         HIPCHK(c, hipMemcpy(c->ca[c->cur], (const char *)host + f19, c7, hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->cb[c->cur], (const char *)host + f19 + c7, c7, hipMemcpyHostToDevice));
     }
@@ -1259,10 +1256,7 @@ flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, doubl
         HIPCHK(c, hipEventRecord(ev[0], c->stream));
         if (c->colour) {
             // both launches of a colour step (phase pass and colour step)
-            if (is_fp64(c))
-                launch_colour_step<double>(c, c->stream, from, false);
-            else
-                launch_colour_step<float>(c, c->stream, from, false);
+            with_storage(c, [&](auto tag) { launch_colour_step<decltype(tag)>(c, c->stream, from, false); });
         } else {
             with_storage(c, [&](auto tag) {
                 using T = decltype(tag);

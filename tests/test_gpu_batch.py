@@ -136,7 +136,7 @@ def test_autotune_picks_and_caches_a_schedule(tmp_path):
     lines = open(cache).read().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
     s2, ms2 = b.autotune(cache, trial_steps=2)
-    assert s2 == s1 and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert s2 == s1 and ms2 == pytest.approx(ms1, rel=1e-4, abs=1e-6)  # cached to 1 ns
     assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 1
     # the tuned batch still steps correctly: compare with singles from here
     singles = [fluxlbm.Lattice(m, precision="fp32", tau=t[3], q_target=t[4], rho_out=t[5])

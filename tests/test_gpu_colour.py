@@ -175,8 +175,11 @@ def crop64():
     return crop
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_colour_crop64_parity(crop64, precision):
+    """FP64 and FP32 to their per-step tolerances; the FP16-deviation mode
+    (momentum populations in FP16, colours in FP32) reported against the
+    FP64 oracle after 1 and 100 steps."""
     mask = crop64
     gamma_ca = 1e-5 * 0.01 * 0.30 * 64 * 64 / (1.0 / 6.0)  # Q* = Ca gamma eps A / mu_w
     lat, orc = colour_pair(mask, precision=precision, tau=1.0, alpha=0.01, beta=0.7,
@@ -191,8 +194,42 @@ def test_colour_crop64_parity(crop64, precision):
     lat.init_colour(na.reshape(-1)[sites], nb.reshape(-1)[sites])
     lat.step(1)
     orc.step(1)
-    assert max(compare(lat, orc, mask)) <= TOL[precision]
+    e1 = compare(lat, orc, mask)
     lat.step(99)
     orc.step(99, record=False)
     ef, ea, eb = compare(lat, orc, mask)
-    assert max(ef, ea, eb) <= (1e-10 if precision == "fp64" else 1e-4)
+    phi_o = oracle_phase(orc, mask)
+    e_phi = float(np.abs(lat.phase() - phi_o).max())
+    print(f"[crop64 {precision}] 1 step: f {e1[0]:.3e} A {e1[1]:.3e} B {e1[2]:.3e}; "
+          f"100 steps: f {ef:.3e} A {ea:.3e} B {eb:.3e} phi {e_phi:.3e}")
+    if precision == "fp16dev":
+        # two 11-bit roundings of every stored deviation per step, |g| << w
+        assert e1[0] <= 5e-5 and max(e1[1:]) <= 1e-6
+        assert ef <= 1e-3 and max(ea, eb) <= 1e-3 and e_phi <= 1e-2
+    else:
+        assert max(e1) <= TOL[precision]
+        assert max(ef, ea, eb) <= (1e-10 if precision == "fp64" else 1e-4)
+
+
+def oracle_phase(orc, mask):
+    _, A, B = orc.get_state()
+    sites = inputs.pore_sites(mask)
+    na = A.reshape(-1, 7)[sites].sum(1)
+    nb = B.reshape(-1, 7)[sites].sum(1)
+    return (na - nb) / (na + nb)
+
+
+@pytest.mark.parametrize("shape,px,py", [((10, 12, 11), 1, 0), ((20, 34, 30), 1, 1)])
+def test_colour_fp16dev_one_step_flux_box(shape, px, py):
+    mask = inputs.random_mask(shape, 0.25, 231)
+    mask[0, 0, 0] = 0
+    lat, orc = colour_pair(mask, precision="fp16dev", q_target=0.002 * shape[1] * shape[2],
+                           periodic_x=px, periodic_y=py)
+    load_colour_state(lat, orc, mask, 232)
+    lat.step(1)
+    h_orc = orc.step(1)
+    ef, ea, eb = compare(lat, orc, mask)
+    # f: two 11-bit roundings of deviations |g| <= 0.05 w; A, B stored in FP32
+    assert ef <= 5e-5 and max(ea, eb) <= 1e-5, (ef, ea, eb)
+    h = lat.history(1)
+    assert abs(h[0, 1] - h_orc[0, 1]) <= 1e-12 * max(1.0, abs(h_orc[0, 1]))
