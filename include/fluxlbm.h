@@ -256,6 +256,14 @@ typedef struct flbm_controller_params {
  * network must outlive the attachment. Flux mode only (else FLBM_ESTATE).
  * Synchronises. */
 flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_controller_params *p);
+/* Inlet density override (a hook for a caller-side controller): while set,
+ * every step uses rho_in = rho_plain + clip(*rho_in_or_null - rho_plain,
+ * +-trust rho0 |Q*| / A), i.e. the plain update of eq. potential still
+ * judges it: |Q_in - Q*| / |Q*| <= trust (Q* at the time of the call).
+ * NULL clears it. It takes precedence over an attached controller's offset.
+ * Flux mode only (else FLBM_ESTATE); a non-finite density or a negative
+ * trust is FLBM_EINVAL. Synchronises; survives steps, not a re-initialisation. */
+flbm_status flbm_set_inlet_density_override(flbm_ctx *c, const double *rho_in_or_null, double trust);
 /* attached flag, released flag, last offset, decisions taken (synchronises) */
 flbm_status flbm_controller_state(flbm_ctx *c, int32_t *active, int32_t *released, double *delta,
                                   int64_t *decisions);

@@ -784,6 +784,24 @@ flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_con
     return FLBM_OK;
 }
 
+flbm_status flbm_set_inlet_density_override(flbm_ctx *c, const double *rho_in_or_null, double trust)
+{
+    if (!c) return FLBM_EINVAL;
+    if (rho_in_or_null && (!std::isfinite(*rho_in_or_null) || !(trust >= 0.0) || !std::isfinite(trust)))
+        return FLBM_EINVAL;
+    if (c->p.z_mode != FLBM_Z_FLUX && rho_in_or_null) return fail(c, FLBM_ESTATE, "the override needs the flux inlet");
+    flbm_status rc = ensure_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const uint32_t on = rho_in_or_null ? 1u : 0u;
+    const double rho = rho_in_or_null ? *rho_in_or_null : 0.0;
+    const double limit = trust * c->p.rho0 * std::fabs(c->p.q_target) / (double)c->lat.a_in;
+    HIPCHK(c, hipMemcpy(&c->st->ovr_rho, &rho, sizeof(rho), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ovr_limit, &limit, sizeof(limit), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ovr_on, &on, sizeof(on), hipMemcpyHostToDevice));
+    return FLBM_OK;
+}
+
 flbm_status flbm_controller_state(flbm_ctx *c, int32_t *active, int32_t *released, double *delta, int64_t *decisions)
 {
     if (!c) return FLBM_EINVAL;

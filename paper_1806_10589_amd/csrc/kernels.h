@@ -61,14 +61,17 @@ struct DevState {
     uint32_t obs_bad;
     int64_t ctrl_steps;   // controller decisions taken
     uint32_t ctrl_released;  // sticky: plain update from now on (tolerance met, or no progress)
-    uint32_t pad_;
+    uint32_t ovr_on;      // 1: the inlet density override below is in force
     double ctrl_best;     // smallest outlet-flux error seen at a 10% improvement
     int64_t ctrl_best_n;  // decision count at that improvement
+    double ovr_rho;       // inlet density override (absolute)
+    double ovr_limit;     // its bound on |rho_in - rho_plain|
 };
 
 // Inlet density minus one for the step that reads parity rd: the update of
 // eq. potential, rho_in = (rho0 Q* + sum_i K_i) / A in deviation form, plus
-// the learned controller's offset (zero unless a controller is attached).
+// the learned controller's offset (zero unless a controller is attached), or
+// a caller's override held within its bound.
 __device__ __forceinline__ double inlet_drho_plain(const DevState *st, int rd, double rho0, int64_t a_in)
 {
     return (rho0 * st->q_target + st->s_carry[rd]) / (double)a_in;
@@ -76,7 +79,14 @@ __device__ __forceinline__ double inlet_drho_plain(const DevState *st, int rd, d
 
 __device__ __forceinline__ double inlet_drho(const DevState *st, int rd, double rho0, int64_t a_in)
 {
-    return inlet_drho_plain(st, rd, rho0, a_in) + st->ctrl_delta;
+    const double plain = inlet_drho_plain(st, rd, rho0, a_in);
+    if (st->ovr_on) {
+        // a caller's inlet density, judged by the plain update: at most
+        // ovr_limit away from it
+        const double d = st->ovr_rho - 1.0 - plain;
+        return plain + fmin(st->ovr_limit, fmax(-st->ovr_limit, d));
+    }
+    return plain + st->ctrl_delta;
 }
 
 struct StepArgs {

@@ -126,6 +126,7 @@ _SIGS = {
     "flbm_set_controller": [_P, _P, _P],
     "flbm_controller_state": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), _DP, _I64P],
     "flbm_controller_trace": [_P, _I32, _P, _P],
+    "flbm_set_inlet_density_override": [_P, _DP, _D],
     "flbm_batch_create": [_I32, _P, ctypes.POINTER(_P)],
     "flbm_batch_destroy": [_P],
     "flbm_batch_set_schedule": [_P, _P],
@@ -429,6 +430,16 @@ def flbm_controller_state(ctx):
     return bool(a.value), bool(r.value), float(d.value), int(n.value)
 
 
+def flbm_set_inlet_density_override(ctx, rho_in, trust: float = 1.0) -> None:
+    if rho_in is None:
+        _check(load_library().flbm_set_inlet_density_override(ctx, None, 0.0), "flbm_set_inlet_density_override",
+               ctx)
+    else:
+        r = _D(float(rho_in))
+        _check(load_library().flbm_set_inlet_density_override(ctx, ctypes.byref(r), float(trust)),
+               "flbm_set_inlet_density_override", ctx)
+
+
 def flbm_controller_trace(ctx, n: int):
     x = np.empty((int(n), 32), dtype=np.float32)
     aux = np.empty((int(n), 4), dtype=np.float64)
@@ -715,6 +726,9 @@ class Lattice:
 
     def controller_trace(self, n):
         return flbm_controller_trace(self.ctx, n)
+
+    def set_inlet_density_override(self, rho_in, trust=1.0):
+        flbm_set_inlet_density_override(self.ctx, rho_in, trust)
 
 
 class Batch:

@@ -229,7 +229,8 @@ def test_colour_fp16dev_one_step_flux_box(shape, px, py):
     lat.step(1)
     h_orc = orc.step(1)
     ef, ea, eb = compare(lat, orc, mask)
-    # f: two 11-bit roundings of deviations |g| <= 0.05 w; A, B stored in FP32
-    assert ef <= 5e-5 and max(ea, eb) <= 1e-5, (ef, ea, eb)
+    # f: two 11-bit roundings of deviations |g| <= 0.05 w; A, B stored in FP32;
+    # the colours inherit that error through u (recolouring uses the FP16-derived velocity)
+    assert max(ef, ea, eb) <= 5e-5, (ef, ea, eb)
     h = lat.history(1)
     assert abs(h[0, 1] - h_orc[0, 1]) <= 1e-12 * max(1.0, abs(h_orc[0, 1]))

@@ -226,3 +226,36 @@ def test_trained_controller_reaches_tolerance_sooner():
         learned += r["learned_steps"]
     print(f"steps to 1e-3: plain {plain}, learned {learned}, gain {plain / learned:.2f}")
     assert learned < plain
+
+
+@pytest.mark.parametrize("trust", [0.5, 100.0])
+def test_inlet_density_override_against_oracle(trust):
+    # a caller's inlet density, judged by the plain update: clipped to within
+    # trust |Q*| of the plain flux (trust 0.5), or taken as is (trust 100)
+    mask = _mask()
+    q = 0.02
+    lat, orc = pair(mask, precision="fp64", tau=0.9, q_target=q)
+    lat.init_equilibrium()
+    orc.init_equilibrium()
+    rho_hat = 1.002
+    lat.set_inlet_density_override(rho_hat, trust)
+    limit = trust * q / orc.a_in
+    rows = []
+    for _ in range(60):
+        plain = orc.plain_inlet_density()
+        orc.set_inlet_offset(min(limit, max(-limit, rho_hat - plain)))
+        rows.append(orc.step(1)[0])
+    ho = np.array(rows)
+    lat.step(60)
+    hg = lat.history(60)
+    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 1e-12
+    assert np.max(np.abs(hg[:, 1] - ho[:, 1])) <= 1e-11
+    assert np.max(np.abs(hg[:, 2] - ho[:, 2])) <= 1e-11
+    if trust > 10:
+        assert np.allclose(hg[:, 0], rho_hat, rtol=0, atol=1e-14)
+    else:
+        assert np.allclose(np.abs(hg[:, 1] - q), trust * q, rtol=1e-9)
+    lat.set_inlet_density_override(None)
+    lat.step(5)
+    assert np.allclose(lat.history(5)[:, 1], q, rtol=1e-10)
+    lat.close()
