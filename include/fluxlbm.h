@@ -298,11 +298,13 @@ typedef struct flbm_schedule {
     int32_t order;          /* FLBM_ORDER_* */
     int32_t tiles_per_item; /* consecutive tiles of one sample per work item (>= 1) */
     int32_t chunk;          /* steps per captured graph (>= 1; graphs are used when even) */
+    int32_t occupancy;      /* 0: the compiler's register budget; 8: at most 64 VGPRs (8 waves per
+                               SIMD); only for grid 0 with one tile per item */
 } flbm_schedule;
 
 /* samples: n context pointers (not copied beyond the call's lifetime of the
  * array; the contexts themselves must outlive the batch). Default schedule:
- * one block per item, interleaved, 4 tiles per item, chunk 64. */
+ * one block per item, interleaved, 4 tiles per item, chunk 64, compiler budget. */
 flbm_status flbm_batch_create(int32_t n, flbm_ctx *const *samples, flbm_batch **out);
 flbm_status flbm_batch_destroy(flbm_batch *b);
 flbm_status flbm_batch_set_schedule(flbm_batch *b, const flbm_schedule *s);
@@ -317,9 +319,10 @@ flbm_status flbm_batch_sync(flbm_batch *b, int32_t *first_unstable);
 flbm_status flbm_batch_time(flbm_batch *b, int32_t n, double *ms_per_step);
 /* Choose the schedule (persistent grid 0 / 2 / 4 / 8 / 16 blocks per compute
  * unit, the three orders, 1 / 4 / 16 tiles per item) by timing trial_steps
- * launches of each (1 + trial_steps steps of every sample per candidate: the
- * samples advance), or take it from cache_path (text lines
- * "arch precision log2(sites) grid order tiles_per_item ms"; NULL: no cache),
+ * launches of each, with both register budgets for one block per single-tile
+ * item (1 + trial_steps steps of every sample per candidate: the samples
+ * advance), or take it from cache_path (text lines "arch precision
+ * log2(sites) grid order tiles_per_item occupancy ms"; NULL: no cache),
  * where a new choice is appended. The chosen schedule is set. */
 flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t trial_steps, flbm_schedule *best,
                                 double *best_ms);

@@ -1,15 +1,18 @@
-// C-ABI of the library: context, device memory, step orchestration.
+// C-ABI of the library: context, device memory, step orchestration, the
+// learned inlet controller and batched stepping.
 //
-// One step is two launches on the caller's stream (Methods, the paragraph
-// after eq. potential: the inlet density is found from the streamed knowns,
-// then the pressure condition is applied, then collision):
-//   1. k_inlet_plane   pulled knowns of the inlet sites -> rho_in (FP64)
-//   2. k_stream_collide pull + boundary conditions + BGK + store, f_a -> f_b
-// With pull streaming the "streamed" values of step t are gathers of the
-// stored state, so step 1 needs no grid-wide barrier inside the step kernel.
-// The buffers alternate every step. Runs of steps are captured once per
-// starting buffer as a HIP graph and replayed; the last step of each run
-// also reduces the watchdog observables.
+// One single-fluid step is one launch on the caller's stream (Methods, the
+// paragraph after eq. potential: the inlet density is found from the
+// streamed knowns, then the pressure condition is applied, then collision):
+// k_stream_collide pulls, applies the boundary conditions with the inlet
+// density of eq. potential, collides (BGK or MRT), stores, and reduces the
+// inlet sum that the next step's inlet sites will pull. With pull streaming
+// the "streamed" values of a step are gathers of the stored state, so no
+// grid-wide barrier is needed inside a step; k_inlet_plane computes the sum
+// from the state only after the host has written it. The colour model adds
+// a phase pass before its step kernel. The buffers alternate every step.
+// Runs of steps are captured once per starting buffer as a HIP graph and
+// replayed; the last step of each run also reduces the watchdog observables.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1437,7 +1440,30 @@ template <typename T, bool MRT>
 void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
 {
     const int grid = b->sched.grid > 0 ? std::min(b->sched.grid, b->n_work) : b->n_work;
-    if (b->use_buf) {
+    if (b->sched.grid == 0 && b->sched.tiles_per_item == 1) {
+        // one tile per block: the loop-free kernel, in the chosen register budget
+        const dim3 g(b->n_work), blk(SC_BLOCK);
+        const bool o8 = b->sched.occupancy == 8;
+#define FLBM_BATCH_TILE(OB, BU)                                                                           \
+    do {                                                                                                  \
+        if (o8)                                                                                           \
+            hipLaunchKernelGGL((k_batch_tile8<T, OB, BU, MRT>), g, blk, 0, s, b->d_tab, b->d_work, parity); \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_batch_tile<T, OB, BU, MRT>), g, blk, 0, s, b->d_tab, b->d_work, parity);  \
+    } while (0)
+        if (b->use_buf) {
+            if (obs)
+                FLBM_BATCH_TILE(true, true);
+            else
+                FLBM_BATCH_TILE(false, true);
+        } else {
+            if (obs)
+                FLBM_BATCH_TILE(true, false);
+            else
+                FLBM_BATCH_TILE(false, false);
+        }
+#undef FLBM_BATCH_TILE
+    } else if (b->use_buf) {
         if (obs)
             hipLaunchKernelGGL((k_batch_step<T, true, true, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
                                b->d_work, b->n_work, parity);
@@ -1498,7 +1524,7 @@ void batch_advance(flbm_batch *b, int k)
 flbm_status batch_check_schedule(const flbm_schedule *s)
 {
     if (!s || s->grid < 0 || s->tiles_per_item < 1 || s->chunk < 1 || s->order < FLBM_ORDER_SAMPLE ||
-        s->order > FLBM_ORDER_LARGEST)
+        s->order > FLBM_ORDER_LARGEST || (s->occupancy != 0 && s->occupancy != 8))
         return FLBM_EINVAL;
     return FLBM_OK;
 }
@@ -1532,7 +1558,7 @@ flbm_status flbm_batch_create(int32_t n, flbm_ctx *const *samples, flbm_batch **
     b->use_buf = c0->use_buf;
     b->precision = c0->p.precision;
     b->model = c0->p.model;
-    b->sched = flbm_schedule{0, FLBM_ORDER_INTERLEAVE, 4, 64};
+    b->sched = flbm_schedule{0, FLBM_ORDER_INTERLEAVE, 4, 64, 0};
     if (hipSetDevice(b->device) != hipSuccess || hipMalloc(&b->d_tab, n * sizeof(BatchSample)) != hipSuccess) {
         delete b;
         return FLBM_ENOMEM;
@@ -1667,12 +1693,12 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
         FILE *fp = std::fopen(cache_path, "r");
         if (fp) {
             char a[64];
-            int p, bk, g, o, t;
+            int p, bk, g, o, t, occ;
             double ms;
-            while (std::fscanf(fp, "%63s %d %d %d %d %d %lf", a, &p, &bk, &g, &o, &t, &ms) == 7) {
+            while (std::fscanf(fp, "%63s %d %d %d %d %d %d %lf", a, &p, &bk, &g, &o, &t, &occ, &ms) == 8) {
                 if (arch == a && p == prec && bk == bucket) {
                     std::fclose(fp);
-                    flbm_schedule s{g, o, t, chunk};
+                    flbm_schedule s{g, o, t, chunk, occ};
                     flbm_status rc = flbm_batch_set_schedule(b, &s);
                     if (rc) return rc;
                     if (best) *best = s;
@@ -1691,27 +1717,29 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
     double bms = 1e300;
     for (int g : grids)
         for (int o : orders)
-            for (int t : tpis) {
-                flbm_schedule s{g, o, t, chunk};
-                flbm_status rc = flbm_batch_set_schedule(b, &s);
-                if (rc) return rc;
-                double ms = 0.0;
-                rc = flbm_batch_time(b, 1, &ms);  // warm-up
-                if (rc) return rc;
-                rc = flbm_batch_time(b, trial_steps, &ms);
-                if (rc) return rc;
-                if (ms < bms) {
-                    bms = ms;
-                    bs = s;
+            for (int t : tpis)
+                for (int occ : {0, 8}) {
+                    if (occ == 8 && !(g == 0 && t == 1)) continue;  // a budget only the loop-free kernel has
+                    flbm_schedule s{g, o, t, chunk, occ};
+                    flbm_status rc = flbm_batch_set_schedule(b, &s);
+                    if (rc) return rc;
+                    double ms = 0.0;
+                    rc = flbm_batch_time(b, 1, &ms);  // warm-up
+                    if (rc) return rc;
+                    rc = flbm_batch_time(b, trial_steps, &ms);
+                    if (rc) return rc;
+                    if (ms < bms) {
+                        bms = ms;
+                        bs = s;
+                    }
                 }
-            }
     flbm_status rc = flbm_batch_set_schedule(b, &bs);
     if (rc) return rc;
     if (cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
         if (fp) {
-            std::fprintf(fp, "%s %d %d %d %d %d %.6f\n", arch.c_str(), prec, bucket, bs.grid, bs.order,
-                         bs.tiles_per_item, bms);
+            std::fprintf(fp, "%s %d %d %d %d %d %d %.6f\n", arch.c_str(), prec, bucket, bs.grid, bs.order,
+                         bs.tiles_per_item, bs.occupancy, bms);
             std::fclose(fp);
         }
     }

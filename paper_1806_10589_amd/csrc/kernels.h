@@ -491,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
 // COLOUR: also the tile's sums of the two colour densities.
 template <int NT, bool OBS, bool COLOUR = false>
 __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_out, double s_next, double m,
-                                              float u2max, uint32_t bad, const StepArgs &a,
+                                              float u2max, uint32_t bad, const StepArgs &a, const int rd,
                                               double na_sum = 0.0, double nb_sum = 0.0)
 {
     __shared__ double lds[NT / 64];
@@ -563,10 +563,10 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
         const int64_t t = st->step;
         double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
         if (a.flux_mode) {
-            h[0] = 1.0 + inlet_drho(st, a.rd, a.rho0, a.a_in);
+            h[0] = 1.0 + inlet_drho(st, rd, a.rho0, a.a_in);
             h[1] = ti;
             h[2] = to;
-            st->s_carry[a.rd ^ 1] = tn;
+            st->s_carry[rd ^ 1] = tn;
         } else {
             h[0] = h[1] = h[2] = __builtin_nan("");
         }
@@ -592,7 +592,7 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
 template <typename T, bool OBS, bool BUF, bool MRT>
 __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__restrict__ fin,
                                                     T *__restrict__ fout, const int32_t *__restrict__ nbr,
-                                                    const StepArgs &a)
+                                                    const StepArgs &a, const int rd)
 {
     using R = typename Compute<T>::type;
     constexpr int V = SC_V;
@@ -640,7 +640,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
 
     double uz_in = 0.0, uz_out = 0.0;
     if (tile < a.nt_in) {
-        const double drho_in = inlet_drho(a.st, a.rd, a.rho0, a.a_in);
+        const double drho_in = inlet_drho(a.st, rd, a.rho0, a.a_in);
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (s0 + v < a.a_in) uz_in += inlet_condition(g[v], drho_in, a.rho0);
@@ -713,7 +713,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         }
     }
 
-    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a);
+    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, rd);
 }
 
 template <typename T, bool OBS, bool BUF, bool MRT = false>
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
                                                              const int32_t *__restrict__ nbr,
                                                              StepArgs a)
 {
-    stream_collide_tile<T, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a);
+    stream_collide_tile<T, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a, a.rd);
 }
 
 // Batched step: many lattices in one launch. Each lattice keeps its own
@@ -748,15 +748,46 @@ __global__ __launch_bounds__(SC_BLOCK) void k_batch_step(const BatchSample *__re
     for (int w = (int)blockIdx.x; w < n_work; w += (int)gridDim.x) {
         const BatchItem it = work[w];
         const BatchSample *S = tab + it.sample;
-        StepArgs a = S->a;
-        a.rd ^= parity;
+        const StepArgs a = S->a;
+        const int rd = a.rd ^ parity;
         const T *fin = (const T *)(parity ? S->f1 : S->f0);
         T *fout = (T *)(parity ? S->f0 : S->f1);
         for (int t = it.t0; t < it.t1; ++t) {
-            stream_collide_tile<T, OBS, BUF, MRT>(t, fin, fout, S->nbr, a);
+            stream_collide_tile<T, OBS, BUF, MRT>(t, fin, fout, S->nbr, a, rd);
             __syncthreads();  // the tile's LDS reductions are reused by the next tile
         }
     }
+}
+
+// The same work with one single-tile item per block and no loop: the
+// arguments then stay in scalar registers as in the single-lattice kernel
+// (the loop of the persistent form costs registers and occupancy). Two
+// register budgets: the compiler's choice, or at most 64 VGPRs (8 waves per
+// SIMD, at the price of a few spilled registers); the autotuner picks.
+template <typename T, bool OBS, bool BUF, bool MRT>
+__device__ __forceinline__ void batch_tile_body(const BatchSample *__restrict__ tab,
+                                                const BatchItem *__restrict__ work, int32_t parity)
+{
+    const BatchItem it = work[blockIdx.x];
+    const BatchSample *S = tab + it.sample;
+    const StepArgs a = S->a;
+    const T *fin = (const T *)(parity ? S->f1 : S->f0);
+    T *fout = (T *)(parity ? S->f0 : S->f1);
+    stream_collide_tile<T, OBS, BUF, MRT>(it.t0, fin, fout, S->nbr, a, a.rd ^ parity);
+}
+
+template <typename T, bool OBS, bool BUF, bool MRT>
+__global__ __launch_bounds__(SC_BLOCK) void k_batch_tile(const BatchSample *__restrict__ tab,
+                                                         const BatchItem *__restrict__ work, int32_t parity)
+{
+    batch_tile_body<T, OBS, BUF, MRT>(tab, work, parity);
+}
+
+template <typename T, bool OBS, bool BUF, bool MRT>
+__global__ __launch_bounds__(SC_BLOCK, 8) void k_batch_tile8(const BatchSample *__restrict__ tab,
+                                                             const BatchItem *__restrict__ work, int32_t parity)
+{
+    batch_tile_body<T, OBS, BUF, MRT>(tab, work, parity);
 }
 
 // Reduce the per-tile observables of the last step into its history record

@@ -53,7 +53,7 @@ class flbm_controller_params(ctypes.Structure):
 
 class flbm_schedule(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("order", ctypes.c_int32), ("tiles_per_item", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("occupancy", ctypes.c_int32)]
 
 
 FLBM_ORDER_SAMPLE, FLBM_ORDER_INTERLEAVE, FLBM_ORDER_LARGEST = 0, 1, 2
@@ -762,12 +762,14 @@ class Batch:
     @property
     def schedule(self):
         s = flbm_batch_get_schedule(self.handle)
-        return dict(grid=s.grid, order=s.order, tiles_per_item=s.tiles_per_item, chunk=s.chunk)
+        return dict(grid=s.grid, order=s.order, tiles_per_item=s.tiles_per_item, chunk=s.chunk,
+                    occupancy=s.occupancy)
 
-    def set_schedule(self, grid=0, order=FLBM_ORDER_INTERLEAVE, tiles_per_item=4, chunk=64):
-        flbm_batch_set_schedule(self.handle, flbm_schedule(grid, order, tiles_per_item, chunk))
+    def set_schedule(self, grid=0, order=FLBM_ORDER_INTERLEAVE, tiles_per_item=4, chunk=64, occupancy=0):
+        flbm_batch_set_schedule(self.handle, flbm_schedule(grid, order, tiles_per_item, chunk, occupancy))
 
     def autotune(self, cache_path=None, trial_steps=5):
         s, ms = flbm_batch_autotune(self.handle, cache_path, trial_steps)
-        return dict(grid=s.grid, order=s.order, tiles_per_item=s.tiles_per_item, chunk=s.chunk), ms
+        return dict(grid=s.grid, order=s.order, tiles_per_item=s.tiles_per_item, chunk=s.chunk,
+                    occupancy=s.occupancy), ms
 

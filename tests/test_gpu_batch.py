@@ -42,6 +42,8 @@ def _lattices(precision, model="bgk"):
 
 
 SCHEDULES = [
+    dict(grid=0, order=fluxlbm.FLBM_ORDER_INTERLEAVE, tiles_per_item=1, chunk=8, occupancy=0),
+    dict(grid=0, order=fluxlbm.FLBM_ORDER_SAMPLE, tiles_per_item=1, chunk=8, occupancy=8),
     dict(grid=0, order=fluxlbm.FLBM_ORDER_INTERLEAVE, tiles_per_item=4, chunk=8),
     dict(grid=3, order=fluxlbm.FLBM_ORDER_SAMPLE, tiles_per_item=1, chunk=6),
     dict(grid=64, order=fluxlbm.FLBM_ORDER_LARGEST, tiles_per_item=3, chunk=5),
@@ -133,6 +135,7 @@ def test_autotune_picks_and_caches_a_schedule(tmp_path):
     cache = str(tmp_path / "sched.txt")
     s1, ms1 = b.autotune(cache, trial_steps=2)
     assert ms1 > 0 and s1["tiles_per_item"] in (1, 4, 16) and s1["order"] in (0, 1, 2)
+    assert s1["occupancy"] in (0, 8)
     lines = open(cache).read().split("\n")
     assert len([l for l in lines if l.strip()]) == 1
     s2, ms2 = b.autotune(cache, trial_steps=2)

@@ -254,7 +254,9 @@ def test_inlet_density_override_against_oracle(trust):
     if trust > 10:
         assert np.allclose(hg[:, 0], rho_hat, rtol=0, atol=1e-14)
     else:
-        assert np.allclose(np.abs(hg[:, 1] - q), trust * q, rtol=1e-9)
+        dev = np.abs(hg[:, 1] - q)
+        assert np.all(dev <= trust * q * (1 + 1e-9))
+        assert np.allclose(dev[:40], trust * q, rtol=1e-9)   # clipped while the plain density is far
     lat.set_inlet_density_override(None)
     lat.step(5)
     assert np.allclose(lat.history(5)[:, 1], q, rtol=1e-10)
