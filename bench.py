@@ -165,6 +165,14 @@ def run_batch(args, cfg):
     rc, bad = b.sync()
     mlups = n_total * args.steps / (ms_total * 1e-3) / 1e6
     ms_kernel = b.time(args.profile_steps)
+    # the same samples stepped one after another by their own launches
+    k_seq = max(10, args.steps // 10)
+    e0.record(stream)
+    for l in lats:
+        l.step(k_seq)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1) / k_seq
     bpl = bytes_per_lup(cfg["precision"])
     achieved = n_total * bpl / (ms_kernel * 1e-3) / 1e9
     out = {
@@ -190,6 +198,7 @@ def run_batch(args, cfg):
             "schedule": sched,
         },
         "status": "ok" if rc == fluxlbm.FLBM_OK else f"unstable (sample {bad})",
+        "sequential_ms_per_step": round(ms_seq, 5),
         "roofline": {
             "bound": "hbm",
             "achieved": round(achieved, 1),

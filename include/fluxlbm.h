@@ -220,58 +220,61 @@ flbm_status flbm_gemm_bf16(const float *A, int64_t a_rs, int64_t a_cs, const flo
 typedef struct flbm_controller_params {
     float geometry[15];   /* static inputs 0..14 of the network (sample and inlet-slice statistics) */
     float reserved;
-    double drho_ref;      /* reference inlet-outlet density difference (input 31, proposal) */
+    double drho_ref;      /* reference inlet-outlet density difference (input 31, absolute proposal) */
     double gain;          /* fraction of the step from the plain density to the proposal taken */
     double trust0;        /* initial bound on |Q_in - Q*| / Q* that a proposal may cause */
-    double release_tol;   /* two-step mean |Q_out - Q*| / Q* that returns control to the
+    double release_tol;   /* period-mean |Q_out - Q*| / Q* that returns control to the
                              plain update for good */
-    int32_t trust_steps;  /* the bound decays linearly to zero over this many steps */
+    int32_t trust_decisions; /* the bound decays linearly to zero over this many decisions */
     int32_t relative;     /* 0: r = log(drho_inf / drho_ref); 1: r = log(drho_inf / drho) */
-    int32_t stall_steps;  /* > 0: release when the outlet error has not improved by 10 %
-                             over this many decisions */
-    int32_t reserved2;
+    int32_t stall_decisions; /* > 0: release when the outlet error has not improved by 10 %
+                                over this many decisions */
+    int32_t period;       /* steps per decision (>= 1; even values average the period-two
+                             oscillation of the outlet flux) */
 } flbm_controller_params;
 
 /* Attach (net != NULL) or detach (net == NULL) the controller. While
- * attached, after every step the network reads 32 inputs: the 15 geometry
- * values, the outlet-flux errors (Qbar_out - Q*) / |Q*| clipped to [-2, 2]
- * at the lags 1, 2, 3, 6, 11, 20, 36, 65, 119, 215, 391, 710, 1290, 2345,
- * 4260, 7740 steps back (Qbar the mean of two consecutive steps, 0 before
- * the first step), and log10(drho / drho_ref) / 3 clipped to [-1, 1] (-1 if
- * drho <= 0), drho = rho_in - rho_out of the last step. Its output r is
- * the predicted steady density difference drho_inf, either absolute
- * (relative = 0: r = log(drho_inf / drho_ref) clipped to [-4, 4], proposal
- * rho_hat = rho_out + drho_ref exp(r)) or as the remaining relative rise
- * (relative = 1: r = log(drho_inf / drho) clipped to [-2, 3], proposal
- * rho_hat = rho_out + drho exp(r); no offset while drho <= 0). The next
- * step uses
+ * attached, it sums the outlet flux over periods of `period` steps and takes
+ * a decision at the end of each period. The network reads 32 inputs: the 15
+ * geometry values, the errors (Qbar - Q*) / |Q*| clipped to [-2, 2] of the
+ * period-mean outlet flux Qbar at lags 1, 2, 3, 4, 6, 8, 11, 16, 22, 32, 45,
+ * 64, 90, 128, 180, 250 periods back (0 before the first step), and
+ * log10(drho / drho_ref) / 3 clipped to [-1, 1] (-1 if drho <= 0), drho =
+ * rho_in - rho_out of the last step. Its output r is the predicted steady
+ * density difference drho_inf, either absolute (relative = 0: r =
+ * log(drho_inf / drho_ref) clipped to [-4, 4], proposal rho_hat = rho_out +
+ * drho_ref exp(r)) or as the remaining relative rise (relative = 1: r =
+ * log(drho_inf / drho) clipped to [-2, 3], rho_hat = rho_out + drho exp(r)).
+ * The proposal is held for the next period; every step in it uses
  *   rho_in = rho_plain + clip(gain (rho_hat - rho_plain), +-bound rho0 |Q*| / A)
- * with rho_plain the update of eq. potential and bound = trust0 (1 -
- * n / trust_steps)^+ after n decisions, i.e. |Q_in - Q*| / Q* <= bound. No
- * offset once the two-step mean outlet error has met release_tol, or (with
- * stall_steps > 0) once it has not fallen below 0.9 times its best value for
- * stall_steps decisions (both sticky), when Q* <= 0, or when the network
- * output or the proposal is not finite. With trust0 = 0 the
- * run is the plain method exactly (the inputs are still recorded). The
- * network must outlive the attachment. Flux mode only (else FLBM_ESTATE).
- * Synchronises. */
+ * with rho_plain the update of eq. potential of that step and bound = trust0
+ * (1 - n / trust_decisions)^+ after n decisions, i.e. |Q_in - Q*| / Q* <=
+ * bound. No proposal once the period-mean outlet error has met release_tol
+ * (after two periods), or (stall_decisions > 0) once it has not fallen below
+ * 0.9 times its best value for stall_decisions decisions (both for good),
+ * when Q* <= 0, when relative and drho <= 0, or when the network output or
+ * the proposal is not finite. With trust0 = 0 the run is the plain method
+ * exactly (the inputs are still recorded). The network must outlive the
+ * attachment. Flux mode only (else FLBM_ESTATE). Synchronises. */
 flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_controller_params *p);
+/* The controller's last n decisions, oldest first (n <= flbm_history_capacity
+ * and n <= the decisions taken since the attachment): inputs x[n][32] (FP32)
+ * and aux[n][4] = {drho, rho_plain, r, offset at the decision step} (FP64).
+ * Synchronises. */
+flbm_status flbm_controller_trace(flbm_ctx *c, int32_t n, float *x, double *aux);
+
 /* Inlet density override (a hook for a caller-side controller): while set,
  * every step uses rho_in = rho_plain + clip(*rho_in_or_null - rho_plain,
  * +-trust rho0 |Q*| / A), i.e. the plain update of eq. potential still
  * judges it: |Q_in - Q*| / |Q*| <= trust (Q* at the time of the call).
- * NULL clears it. It takes precedence over an attached controller's offset.
+ * NULL clears it. It takes precedence over an attached controller's proposal.
  * Flux mode only (else FLBM_ESTATE); a non-finite density or a negative
  * trust is FLBM_EINVAL. Synchronises; survives steps, not a re-initialisation. */
 flbm_status flbm_set_inlet_density_override(flbm_ctx *c, const double *rho_in_or_null, double trust);
-/* attached flag, released flag, last offset, decisions taken (synchronises) */
+/* attached flag, released flag, offset at the last decision, decisions taken
+ * (synchronises) */
 flbm_status flbm_controller_state(flbm_ctx *c, int32_t *active, int32_t *released, double *delta,
                                   int64_t *decisions);
-/* The controller's last n decisions, oldest first (n <= flbm_history_capacity,
- * and decisions taken since the attachment): inputs x[n][32] (FP32) and
- * aux[n][4] = {drho, rho_plain, r, offset} (FP64), decision k taken after
- * step k. Synchronises. */
-flbm_status flbm_controller_trace(flbm_ctx *c, int32_t n, float *x, double *aux);
 
 /* ---------------------------------------------------------------------
  * Batched stepping: many lattices (porous samples of uneven size, each with

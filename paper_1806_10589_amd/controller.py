@@ -34,10 +34,19 @@ DEFAULT_WEIGHTS = os.path.join(HERE, "controller_weights.npz")
 N_IN = 32
 RESERVOIR = 6
 
-# controller settings used for training runs and evaluation; trust_steps and
-# stall_steps default to 4 nz^2 and nz^2 / 8 (nz the lattice length: the
-# charging transient scales with its square)
-DEFAULTS = dict(gain=1.0, trust0=4.0, release_tol=1e-3, relative=True)
+# controller settings used for training runs and evaluation. The decision
+# period scales with the charging time of the sample, which grows as the
+# square of its length nz: period = 2 round(nz^2 / 400) steps (even, so that
+# the period mean averages the period-two oscillation of the outlet flux),
+# so that the inputs (errors at lags counted in periods) look alike across
+# sizes; the trust bound decays over 800 decisions and the progress judge
+# allows 25 decisions without a 10 % improvement.
+DEFAULTS = dict(gain=1.0, trust0=4.0, release_tol=1e-3, relative=True, trust_decisions=800,
+                stall_decisions=25)
+
+
+def decision_period(nz: int) -> int:
+    return max(2, 2 * int(round(nz * nz / 400.0)))
 
 
 # ---------------------------------------------------------------- inputs
@@ -150,13 +159,15 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
                                            reservoir_layers=kw.get("reservoir_layers", RESERVOIR))
         drho_ref *= ref_scale
         nz = mask.shape[0]
+        period = int(s.get("period", decision_period(nz)))
         if net is not None:
             lat.set_controller(net, geom, drho_ref=drho_ref, gain=s["gain"],
                                trust0=s["trust0"] if active else 0.0, release_tol=s["release_tol"],
-                               trust_steps=int(s.get("trust_steps", 4 * nz * nz)),
-                               relative=bool(s["relative"]), stall_steps=int(s.get("stall_steps", nz * nz // 8)))
+                               trust_decisions=int(s["trust_decisions"]), relative=bool(s["relative"]),
+                               stall_decisions=int(s["stall_decisions"]), period=period)
         q = kw["q_target"]
         hist, xs, auxs = [], [], []
+        seen = 0
         t0 = time.perf_counter()
         while lat.step_count < max_steps:
             k = min(chunk, max_steps - lat.step_count)
@@ -164,9 +175,12 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
             h = lat.history(k)
             hist.append(h[:, :3].copy())
             if record and net is not None:
-                x, aux = lat.controller_trace(k)
-                xs.append(x)
-                auxs.append(aux)
+                decisions = lat.controller_state()[3]
+                if decisions > seen:
+                    x, aux = lat.controller_trace(decisions - seen)
+                    xs.append(x)
+                    auxs.append(aux)
+                    seen = decisions
             qo = np.concatenate([hh[:, 2] for hh in hist])
             st = steps_to_tol(qo, q, settle_tol)
             if st is not None and lat.step_count - st >= max(min_margin, margin_frac * st):
@@ -174,12 +188,12 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
         secs = time.perf_counter() - t0
         hist = np.concatenate(hist)
         out = dict(steps=int(lat.step_count), secs=secs, hist=hist, drho_ref=drho_ref, geometry=geom,
-                   steps_to_tol=steps_to_tol(hist[:, 2], q, tol), q_target=q)
+                   steps_to_tol=steps_to_tol(hist[:, 2], q, tol), q_target=q, period=period)
         if net is not None:
             out["controller"] = lat.controller_state()
         if record and net is not None:
-            out["x"] = np.concatenate(xs)
-            out["aux"] = np.concatenate(auxs)
+            out["x"] = np.concatenate(xs) if xs else np.zeros((0, N_IN), np.float32)
+            out["aux"] = np.concatenate(auxs) if auxs else np.zeros((0, 4))
         return out
     finally:
         lat.close()
@@ -224,12 +238,12 @@ def pick_rows(n_rows: int, k: int, seed: int) -> np.ndarray:
 
 def training_family(count: int, seed0: int = 1000):
     """Seeded training samples: sphere packs with edges in {48, 64, 80, 96,
-    128}, porosity in [0.22, 0.40], tau in [0.6, 1.2], Darcy velocity
+    128, 160}, porosity in [0.22, 0.40], tau in [0.6, 1.2], Darcy velocity
     log-uniform in [3e-6, 3e-5]."""
     rng = np.random.default_rng(seed0)
     out = []
     for i in range(count):
-        out.append(dict(n=int(rng.choice([48, 64, 80, 96, 128])), porosity=float(rng.uniform(0.22, 0.40)),
+        out.append(dict(n=int(rng.choice([48, 64, 80, 96, 128, 160])), porosity=float(rng.uniform(0.22, 0.40)),
                         seed=seed0 + 1 + i, tau=float(rng.uniform(0.6, 1.2)),
                         darcy=float(10 ** rng.uniform(math.log10(3e-6), math.log10(3e-5)))))
     return out
@@ -358,7 +372,7 @@ def load_weights(path: str = DEFAULT_WEIGHTS):
 
 def settings_of(meta) -> dict:
     """The controller settings the weights were trained with."""
-    keep = ("relative", "gain", "trust0", "release_tol")
+    keep = ("relative", "gain", "trust0", "release_tol", "trust_decisions", "stall_decisions")
     return {k: v for k, v in meta.get("settings", {}).items() if k in keep}
 
 

@@ -86,6 +86,7 @@ struct flbm_ctx {
     flbm_controller_params ctrl{};
     float *ctrl_feat = nullptr;   // [16] geometry inputs on the device
     float *ctrl_trace = nullptr;  // [HIST_CAP][CTRL_REC] decision records
+    double *ctrl_ring = nullptr;  // [256] period-mean outlet fluxes
 
     // host bookkeeping
     int64_t steps = 0;
@@ -166,6 +167,7 @@ size_t carve(flbm_ctx *c, char *base)
     char *fl = take((size_t)4 * npad * sizeof(double));
     char *cf = take(16 * sizeof(float));
     char *ct = take((size_t)HIST_CAP * 40 * sizeof(float));
+    char *cr = take(256 * sizeof(double));
     char *cc[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     char *on = nullptr, *ob2 = nullptr;
     if (c->colour) {
@@ -191,6 +193,7 @@ size_t carve(flbm_ctx *c, char *base)
         c->fields = (double *)fl;
         c->ctrl_feat = (float *)cf;
         c->ctrl_trace = (float *)ct;
+        c->ctrl_ring = (double *)cr;
         if (c->colour) {
             c->ca[0] = cc[0];
             c->ca[1] = cc[1];
@@ -365,29 +368,34 @@ void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
     with_storage(c, [&](auto tag) { launch_step<decltype(tag)>(c, s, from, obs); });
 }
 
-// Learned inlet controller (one workgroup, after each step kernel). From the
-// step history it builds the network's inputs -- 15 geometry values, 16
-// outlet-flux errors at log-spaced lags and the scale of the current
-// inlet-outlet density difference -- and runs the network (MFMA, BF16
-// operands, FP32 accumulation). The output is the predicted steady
-// inlet-outlet density difference, as the log of its ratio to a reference;
-// the step from the plain density of the next step towards that proposal is
-// clipped so that the inlet flux stays within the decaying trust bound, and
-// dropped once the outlet flux has met the release tolerance, for Q* <= 0, or
-// when it is not finite.
-constexpr int CTRL_LAGS[16] = {1, 2, 3, 6, 11, 20, 36, 65, 119, 215, 391, 710, 1290, 2345, 4260, 7740};
-constexpr int CTRL_REC = 40;  // floats per trace record: x[32], then 4 doubles
+// Learned inlet controller (one workgroup, launched after every step
+// kernel). Every step it adds the outlet flux to the current period's sum;
+// every `period` steps it closes the period (pushing its mean outlet flux into
+// a ring) and decides: it builds the network's inputs -- 15 geometry values,
+// the period-mean outlet-flux errors at 16 log-spaced lags (in periods) and
+// the scale of the current inlet-outlet density difference -- runs the
+// network (MFMA, BF16 operands, FP32 accumulation) and holds the proposed
+// inlet density with the decaying trust bound for the next period; the step
+// kernel moves the plain density of eq. potential towards it by at most that
+// bound every step. No proposal once the outlet flux has met the release
+// tolerance or stopped improving (for good), for Q* <= 0, or when the output
+// is not finite. With the period scaled to the charging time of the sample
+// (which grows as its length squared), the inputs look alike across sizes.
+constexpr int CTRL_LAGS[16] = {1, 2, 3, 4, 6, 8, 11, 16, 22, 32, 45, 64, 90, 128, 180, 250};
+constexpr int CTRL_RING = 256;  // period means kept (> the longest lag)
+constexpr int CTRL_REC = 40;    // floats per trace record: x[32], then 4 doubles
 
 struct CtrlArgs {
     DevState *st;
     const double *hist;
-    float *trace;  // [HIST_CAP][CTRL_REC]
+    double *ring;  // [CTRL_RING] period-mean outlet fluxes
+    float *trace;  // [HIST_CAP][CTRL_REC], one record per decision
     int32_t hist_cap;
-    int32_t trust_steps;
+    int32_t trust_decisions;
     int32_t rd_next;
     int32_t relative;
-    int32_t stall_steps;
-    int32_t pad_;
+    int32_t stall_decisions;
+    int32_t period;
     const float *params;
     const float *geometry;
     double rho0, a_in, drho_ref, gain, trust0, release_tol;
@@ -399,14 +407,27 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
     __shared__ float h1[mlp::N_HID], h2[mlp::N_HID];
     DevState *st = c.st;
     const int64_t t = st->step;  // steps completed; the last one has index t - 1
+    if (t < 1) return;
+    const bool decide = (t % c.period) == 0;
+    if (threadIdx.x == 0) {
+        const double q = c.hist[((t - 1) % c.hist_cap) * HIST_STRIDE + 2];
+        double acc = st->ctrl_acc + (isfinite(q) ? q : 0.0);
+        if (decide) {
+            c.ring[st->ctrl_periods % CTRL_RING] = acc / (double)c.period;
+            st->ctrl_periods += 1;
+            acc = 0.0;
+        }
+        st->ctrl_acc = acc;
+    }
+    if (!decide) return;
+    __syncthreads();
+    const int64_t np = st->ctrl_periods;
     const double qs = st->q_target;
     const double qn = qs != 0.0 ? fabs(qs) : 1.0;
-    auto qout = [&](int64_t k) -> double {  // outlet flux of step k; rest before the first step
-        if (k < 0) return 0.0;
-        const double v = c.hist[(k % c.hist_cap) * HIST_STRIDE + 2];
-        return isfinite(v) ? v : 0.0;
+    auto qbar = [&](int64_t k) -> double {  // mean outlet flux of period k; rest before the first
+        return k >= 0 ? c.ring[k % CTRL_RING] : 0.0;
     };
-    const double rin = t >= 1 ? c.hist[((t - 1) % c.hist_cap) * HIST_STRIDE + 0] : 1.0 + st->drho_out;
+    const double rin = c.hist[((t - 1) % c.hist_cap) * HIST_STRIDE + 0];
     const double drho = rin - 1.0 - st->drho_out;
     if (threadIdx.x < mlp::N_IN) {
         const int i = threadIdx.x;
@@ -414,8 +435,7 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
         if (i < 15) {
             v = c.geometry[i];
         } else if (i < 31) {
-            const int lag = CTRL_LAGS[i - 15];
-            const double e = (0.5 * (qout(t - lag) + qout(t - lag - 1)) - qs) / qn;
+            const double e = (qbar(np - CTRL_LAGS[i - 15]) - qs) / qn;
             v = (float)fmin(2.0, fmax(-2.0, e));
         } else {
             const double lg = drho > 0.0 ? log10(drho / c.drho_ref) / 3.0 : -1.0;
@@ -425,31 +445,35 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
     }
     __syncthreads();
     const float y = mlp::forward_one(c.params, x, h1, h2);
-    float *rec = c.trace + (size_t)((t - 1 + c.hist_cap) % c.hist_cap) * CTRL_REC;
+    const int64_t n = st->ctrl_steps;  // decisions taken before this one
+    float *rec = c.trace + (size_t)(n % c.hist_cap) * CTRL_REC;
     if (threadIdx.x < mlp::N_IN) rec[threadIdx.x] = x[threadIdx.x];
     if (threadIdx.x == 0) {
-        const int64_t n = st->ctrl_steps;
-        const double e2 = fabs(0.5 * (qout(t - 1) + qout(t - 2)) - qs) / qn;
-        if (t >= 2 && e2 <= c.release_tol) st->ctrl_released = 1u;
-        // progress judge: the error must fall by 10 % within stall_steps decisions
-        if (n == 0 || e2 < 0.9 * st->ctrl_best) {
-            st->ctrl_best = e2;
+        const double e = fabs(qbar(np - 1) - qs) / qn;
+        if (np >= 2 && e <= c.release_tol) st->ctrl_released = 1u;
+        // progress judge: the error must fall by 10 % within stall_decisions decisions
+        if (n == 0 || e < 0.9 * st->ctrl_best) {
+            st->ctrl_best = e;
             st->ctrl_best_n = n;
-        } else if (c.stall_steps > 0 && n - st->ctrl_best_n >= c.stall_steps) {
+        } else if (c.stall_decisions > 0 && n - st->ctrl_best_n >= c.stall_decisions) {
             st->ctrl_released = 1u;
         }
         const double bound =
-            c.trust_steps > 0 ? c.trust0 * fmax(0.0, 1.0 - (double)n / (double)c.trust_steps) : 0.0;
+            c.trust_decisions > 0 ? c.trust0 * fmax(0.0, 1.0 - (double)n / (double)c.trust_decisions) : 0.0;
         const double limit = bound * c.rho0 * qn / c.a_in;
         const double rho_plain = 1.0 + inlet_drho_plain(st, c.rd_next, c.rho0, (int64_t)c.a_in);
         const double r = c.relative ? fmin(3.0, fmax(-2.0, (double)y)) : fmin(4.0, fmax(-4.0, (double)y));
         const double rho_hat = 1.0 + st->drho_out + (c.relative ? drho : c.drho_ref) * exp(r);
-        double delta = c.gain * (rho_hat - rho_plain);
         // a non-finite output is dropped before clipping (fmin/fmax would
         // turn a NaN into a bound)
-        if (!isfinite(y) || !isfinite(delta) || !(qs > 0.0) || st->ctrl_released || (c.relative && !(drho > 0.0)))
-            delta = 0.0;
-        delta = fmin(limit, fmax(-limit, delta));
+        const bool on = isfinite(y) && isfinite(rho_hat) && qs > 0.0 && !st->ctrl_released &&
+                        !(c.relative && !(drho > 0.0)) && limit > 0.0;
+        double delta = 0.0;
+        if (on) delta = fmin(limit, fmax(-limit, c.gain * (rho_hat - rho_plain)));
+        st->ctrl_rho = on ? rho_hat : 0.0;
+        st->ctrl_limit = on ? limit : 0.0;
+        st->ctrl_gain = c.gain;
+        st->ctrl_on = on ? 1u : 0u;
         st->ctrl_delta = delta;
         st->ctrl_steps = n + 1;
         double *aux = (double *)(rec + 32);
@@ -465,12 +489,14 @@ void launch_controller(flbm_ctx *c, hipStream_t s, int rd_next)
     CtrlArgs a{};
     a.st = c->st;
     a.hist = c->hist;
+    a.ring = c->ctrl_ring;
     a.trace = c->ctrl_trace;
     a.hist_cap = HIST_CAP;
-    a.trust_steps = c->ctrl.trust_steps;
+    a.trust_decisions = c->ctrl.trust_decisions;
     a.rd_next = rd_next;
     a.relative = c->ctrl.relative;
-    a.stall_steps = c->ctrl.stall_steps;
+    a.stall_decisions = c->ctrl.stall_decisions;
+    a.period = c->ctrl.period;
     a.params = c->ctrl_net->params;
     a.geometry = c->ctrl_feat;
     a.rho0 = c->p.rho0;
@@ -764,9 +790,9 @@ flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_con
     HIPCHK(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     if (net) {
-        if (!(p->trust0 >= 0.0) || !std::isfinite(p->gain) || p->trust_steps < 0 || !(p->release_tol >= 0.0) ||
-            !(p->drho_ref > 0.0) || !std::isfinite(p->drho_ref) || p->stall_steps < 0 ||
-            (p->relative != 0 && p->relative != 1))
+        if (!(p->trust0 >= 0.0) || !std::isfinite(p->gain) || p->trust_decisions < 0 || !(p->release_tol >= 0.0) ||
+            !(p->drho_ref > 0.0) || !std::isfinite(p->drho_ref) || p->stall_decisions < 0 ||
+            (p->relative != 0 && p->relative != 1) || p->period < 1)
             return fail(c, FLBM_EINVAL, "bad controller parameters");
         c->ctrl = *p;
         c->ctrl_net = net;
@@ -784,6 +810,9 @@ flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_con
     HIPCHK(c, hipMemcpy(&c->st->ctrl_released, &z32, sizeof(z32), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(&c->st->ctrl_best, &zero, sizeof(zero), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(&c->st->ctrl_best_n, &z64, sizeof(z64), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_on, &z32, sizeof(z32), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_acc, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(&c->st->ctrl_periods, &z64, sizeof(z64), hipMemcpyHostToDevice));
     return FLBM_OK;
 }
 
@@ -836,7 +865,7 @@ flbm_status flbm_controller_trace(flbm_ctx *c, int32_t n, float *x, double *aux)
     std::vector<float> rec((size_t)HIST_CAP * CTRL_REC);
     HIPCHK(c, hipMemcpy(rec.data(), c->ctrl_trace, rec.size() * sizeof(float), hipMemcpyDeviceToHost));
     for (int32_t i = 0; i < n; ++i) {
-        const int64_t k = d.step - n + i;  // decision taken after step k
+        const int64_t k = d.ctrl_steps - n + i;  // decision number
         const float *r = rec.data() + (size_t)(k % HIST_CAP) * CTRL_REC;
         std::memcpy(x + (size_t)i * 32, r, 32 * sizeof(float));
         std::memcpy(aux + (size_t)i * 4, r + 32, 4 * sizeof(double));

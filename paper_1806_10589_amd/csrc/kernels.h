@@ -51,7 +51,7 @@ struct DevState {
     double s_carry[2];    // inlet consistency sum (deviation form) for the next step,
                           // slot = index of the buffer that step reads
     double omega;         // 1/tau (0 turns collision off)
-    double ctrl_delta;    // controller's inlet density offset for the next step (0: plain update)
+    double ctrl_delta;    // controller's offset at its last decision (reporting only)
     double obs_mass;      // on-demand observables
     double obs_umax;
     int64_t step;         // steps completed
@@ -66,12 +66,19 @@ struct DevState {
     int64_t ctrl_best_n;  // decision count at that improvement
     double ovr_rho;       // inlet density override (absolute)
     double ovr_limit;     // its bound on |rho_in - rho_plain|
+    double ctrl_rho;      // the controller's held proposal (absolute inlet density)
+    double ctrl_limit;    // its bound on |rho_in - rho_plain| until the next decision
+    double ctrl_gain;
+    double ctrl_acc;      // sum of the outlet flux over the current decision period
+    int64_t ctrl_periods; // decision periods completed (entries pushed to the period ring)
+    uint32_t ctrl_on;     // 1: the held proposal is in force
+    uint32_t pad2_;
 };
 
 // Inlet density minus one for the step that reads parity rd: the update of
-// eq. potential, rho_in = (rho0 Q* + sum_i K_i) / A in deviation form, plus
-// the learned controller's offset (zero unless a controller is attached), or
-// a caller's override held within its bound.
+// eq. potential, rho_in = (rho0 Q* + sum_i K_i) / A in deviation form, moved
+// towards a caller's override or the learned controller's held proposal by
+// at most the bound that comes with it (the plain update judges both).
 __device__ __forceinline__ double inlet_drho_plain(const DevState *st, int rd, double rho0, int64_t a_in)
 {
     return (rho0 * st->q_target + st->s_carry[rd]) / (double)a_in;
@@ -86,7 +93,12 @@ __device__ __forceinline__ double inlet_drho(const DevState *st, int rd, double 
         const double d = st->ovr_rho - 1.0 - plain;
         return plain + fmin(st->ovr_limit, fmax(-st->ovr_limit, d));
     }
-    return plain + st->ctrl_delta;
+    if (st->ctrl_on) {
+        // the learned controller's held proposal, judged the same way
+        const double d = st->ctrl_gain * (st->ctrl_rho - 1.0 - plain);
+        return plain + fmin(st->ctrl_limit, fmax(-st->ctrl_limit, d));
+    }
+    return plain;
 }
 
 struct StepArgs {

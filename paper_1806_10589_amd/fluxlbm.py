@@ -46,8 +46,8 @@ class flbm_controller_params(ctypes.Structure):
     _fields_ = [
         ("geometry", ctypes.c_float * 15), ("reserved", ctypes.c_float),
         ("drho_ref", ctypes.c_double), ("gain", ctypes.c_double), ("trust0", ctypes.c_double), ("release_tol", ctypes.c_double),
-        ("trust_steps", ctypes.c_int32), ("relative", ctypes.c_int32), ("stall_steps", ctypes.c_int32),
-        ("reserved2", ctypes.c_int32),
+        ("trust_decisions", ctypes.c_int32), ("relative", ctypes.c_int32),
+        ("stall_decisions", ctypes.c_int32), ("period", ctypes.c_int32),
     ]
 
 
@@ -704,7 +704,7 @@ class Lattice:
         return flbm_device_layout(self.ctx)
 
     def set_controller(self, net: "Mlp | None", geometry=None, *, drho_ref=1e-3, gain=1.0, trust0=0.5,
-                       release_tol=1e-3, trust_steps=20000, relative=False, stall_steps=0):
+                       release_tol=1e-3, trust_decisions=20000, relative=False, stall_decisions=0, period=1):
         if net is None:
             flbm_set_controller(self.ctx, None, None)
             self._ctrl_net = None
@@ -716,8 +716,9 @@ class Lattice:
         for i in range(15):
             p.geometry[i] = float(g[i])
         p.drho_ref = float(drho_ref)
-        p.relative, p.stall_steps = int(bool(relative)), int(stall_steps)
-        p.gain, p.trust0, p.release_tol, p.trust_steps = float(gain), float(trust0), float(release_tol), int(trust_steps)
+        p.relative, p.stall_decisions, p.period = int(bool(relative)), int(stall_decisions), int(period)
+        p.gain, p.trust0, p.release_tol = float(gain), float(trust0), float(release_tol)
+        p.trust_decisions = int(trust_decisions)
         flbm_set_controller(self.ctx, net.handle, p)
         self._ctrl_net = net  # the network must outlive the attachment
 

@@ -35,7 +35,7 @@ def _params(seed, b3, scale=0.3):
 GEOM = np.linspace(-0.5, 0.5, 15).astype(np.float32)
 
 
-def _run_pair(gain, trust0, b3, n=80, relative=False, stall_steps=0):
+def _run_pair(gain, trust0, b3, n=80, relative=False, stall=0, period=1, trust_decisions=50):
     mask = _mask()
     q = 0.02
     lat, orc = pair(mask, precision="fp64", tau=0.9, q_target=q)
@@ -44,63 +44,75 @@ def _run_pair(gain, trust0, b3, n=80, relative=False, stall_steps=0):
     params = _params(81, b3)
     net = fluxlbm.Mlp(16)
     net.set_params(params)
-    kw = dict(drho_ref=1e-3, gain=gain, trust0=trust0, release_tol=1e-12, trust_steps=50, relative=relative,
-              stall_steps=stall_steps)
+    kw = dict(drho_ref=1e-3, gain=gain, trust0=trust0, release_tol=1e-12, trust_decisions=trust_decisions,
+              relative=relative, stall_decisions=stall, period=period)
     lat.set_controller(net, GEOM, **kw)
     oc = OracleController(params.astype(np.float64), GEOM, **kw)
     lat.step(n)
     hg = lat.history(n)
     ho = oc.run(orc, n, q_target=q)
-    x, aux = lat.controller_trace(n)
+    x, aux = lat.controller_trace(n // period)
     return lat, orc, net, oc, hg, ho, x, aux, q, kw
 
 
-@pytest.mark.parametrize("relative", [False, True])
-def test_clipped_decisions_match_oracle_exactly(relative):
-    # every proposal lies far above the trust bound, so each offset is the
-    # bound itself: the same FP64 number on both sides, and the two runs stay
-    # equal to rounding
-    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(1.0, 0.5, 8.0, relative=relative)
+@pytest.mark.parametrize("relative,period", [(False, 1), (True, 1), (True, 3)])
+def test_clipped_decisions_match_oracle_exactly(relative, period):
+    # every proposal lies far above the trust bound, so the inlet density of
+    # every controlled step is the plain one plus the bound: the same FP64
+    # number on both sides, and the two runs stay equal to rounding
+    td = 50 // period
+    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(1.0, 0.5, 8.0, relative=relative, period=period,
+                                                         trust_decisions=td)
+    nd = 80 // period
     xo = np.array([r[0] for r in oc.records])
     auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
+    assert len(oc.records) == nd and x.shape == (nd, 32)
     assert np.max(np.abs(x - xo)) <= 1e-6
     assert np.max(np.abs(aux[:, 0] - auxo[:, 0])) <= 1e-12          # drho
     assert np.max(np.abs(aux[:, 1] - auxo[:, 1])) <= 1e-12          # rho_plain
     assert np.max(np.abs(aux[:, 2] - auxo[:, 2])) <= 2e-4 * max(1.0, np.abs(auxo[:, 2]).max())
-    limit = 0.5 * q / orc.a_in * np.maximum(0.0, 1.0 - np.arange(80) / 50.0)
+    limit = 0.5 * q / orc.a_in * np.maximum(0.0, 1.0 - np.arange(nd) / td)
     assert np.allclose(auxo[:, 3], limit, rtol=1e-15, atol=0)        # clipped every time
     assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 1e-15
-    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 1e-12              # rho_in
+    assert np.max(np.abs(hg[:, 0] - ho[:, 0])) <= 1e-12              # rho_in of every step
     assert np.max(np.abs(hg[:, 2] - ho[:, 2])) <= 1e-12              # Q_out
-    assert np.allclose(hg[51:, 1], q, rtol=1e-10)                    # bound gone: plain
+    # each step of a period is held at the bound of the decision before it
+    dev = np.abs(hg[:, 1] - q) / q
+    for k in range(80):
+        d = k // period - 1                      # the decision in force at step k (-1: none yet)
+        want = 0.5 * max(0.0, 1.0 - d / td) if d >= 0 else 0.0
+        assert abs(dev[k] - want) <= 1e-9, (k, dev[k], want)
     active, released, _, decisions = lat.controller_state()
-    assert active and not released and decisions == 80
+    assert active and not released and decisions == nd
     lat.close()
     net.close()
 
 
-@pytest.mark.parametrize("relative", [False, True])
-def test_proportional_decisions_follow_the_rule(relative):
+@pytest.mark.parametrize("relative,period", [(False, 1), (True, 1), (True, 4)])
+def test_proportional_decisions_follow_the_rule(relative, period):
     # offsets inside the bound carry the network's FP32 output: check each
     # device decision against the rule evaluated by the oracle on the
     # device's own record, then the trajectory against the oracle run with
     # the propagated tolerance
-    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(0.2, 50.0, -0.3, relative=relative)
+    lat, orc, net, oc, hg, ho, x, aux, q, kw = _run_pair(0.2, 50.0, -0.3, relative=relative, period=period,
+                                                         trust_decisions=50 // period)
     a_in = orc.a_in
-    for k in range(80):
-        # inputs from the device's own history of Q_out and rho_in
+    nd = 80 // period
+    for k in range(nd):
+        t = (k + 1) * period                     # steps completed at decision k
         ref = OracleController(oc.params, GEOM, **kw)
-        ref.qout = list(hg[:k + 1, 2])
-        ref.rho_in = list(hg[:k + 1, 0])
+        ref.periods = [float(np.mean(hg[j * period:(j + 1) * period, 2])) for j in range(k + 1)]
+        ref.rho_in = list(hg[:t, 0])
         xk, drho = ref.inputs(q, 1.0)
         assert np.max(np.abs(x[k] - xk)) <= 1e-6, k
         assert abs(aux[k, 0] - drho) <= 1e-15
         y = ref.network(x[k].astype(np.float64))
         assert abs(aux[k, 2] - y) <= 2e-4 * max(1.0, abs(y)), k
-        d = ref.offset(aux[k, 2], aux[k, 1], k, False, q_target=q, rho_out=1.0, rho0=1.0, a_in=a_in,
-                       drho=aux[k, 0])
+        hold = ref.proposal(aux[k, 2], aux[k, 0], k, False, q_target=q, rho_out=1.0, rho0=1.0, a_in=a_in)
+        d = ref.offset(hold, aux[k, 1])
         assert abs(aux[k, 3] - d) <= 1e-15 + 1e-12 * abs(d), k
-    assert np.any(np.abs(aux[:50, 3]) > 0) and np.all(aux[50:, 3] == 0.0)
+    td = 50 // period
+    assert np.any(np.abs(aux[:td, 3]) > 0) and np.all(aux[td:, 3] == 0.0)
     auxo = np.array([[r[1], r[2], r[3], r[4]] for r in oc.records])
     scale = (np.abs(aux[:, 0]).max() * math.exp(3.0) if relative else kw["drho_ref"] * math.exp(4.0)) * kw["gain"]
     assert np.max(np.abs(aux[:, 3] - auxo[:, 3])) <= 2e-4 * scale + 1e-12
@@ -128,7 +140,7 @@ def _plain_and_controlled(params, ctrl, steps=300, precision="fp64"):
 
 def test_zero_trust_is_the_plain_method_bitwise():
     (fa, fb, ha, hb, b), net = _plain_and_controlled(
-        _params(91, 2.0), dict(drho_ref=1e-3, trust0=0.0, release_tol=0.0, trust_steps=1000))
+        _params(91, 2.0), dict(drho_ref=1e-3, trust0=0.0, release_tol=0.0, trust_decisions=1000))
     assert np.array_equal(fa, fb)
     assert np.array_equal(ha[:, :3], hb[:, :3])
     x, aux = b.controller_trace(300)
@@ -141,7 +153,7 @@ def test_non_finite_network_falls_back_to_plain():
     p = _params(92, 0.0)
     p[-1] = np.nan
     (fa, fb, ha, hb, b), net = _plain_and_controlled(
-        p, dict(drho_ref=1e-3, trust0=5.0, release_tol=0.0, trust_steps=1000))
+        p, dict(drho_ref=1e-3, trust0=5.0, release_tol=0.0, trust_decisions=1000))
     assert np.array_equal(fa, fb)
     _, aux = b.controller_trace(300)
     assert np.all(np.isnan(aux[:, 2])) and np.all(aux[:, 3] == 0.0)
@@ -151,10 +163,10 @@ def test_non_finite_network_falls_back_to_plain():
 
 def test_trust_bound_clips_and_decays():
     # r = 4 proposes a density far above anything reasonable: every offset is
-    # clipped to the bound, which decays to zero after trust_steps decisions
+    # clipped to the bound, which decays to zero after trust_decisions decisions
     q, trust0, ts = 0.02, 0.2, 100
     (fa, fb, ha, hb, b), net = _plain_and_controlled(
-        _params(93, 50.0), dict(drho_ref=1e-3, trust0=trust0, release_tol=0.0, trust_steps=ts), steps=200)
+        _params(93, 50.0), dict(drho_ref=1e-3, trust0=trust0, release_tol=0.0, trust_decisions=ts), steps=200)
     dev = np.abs(hb[:, 1] - q) / q        # |Q_in - Q*| / Q* per step
     n = np.arange(200)
     bound = trust0 * np.maximum(0.0, 1.0 - (n - 1) / ts)  # step k uses decision k-1
@@ -168,11 +180,11 @@ def test_trust_bound_clips_and_decays():
 
 def test_release_returns_control_for_good():
     (fa, fb, ha, hb, b), net = _plain_and_controlled(
-        _params(94, 50.0), dict(drho_ref=1e-3, trust0=1.0, release_tol=10.0, trust_steps=10 ** 6), steps=50)
+        _params(94, 50.0), dict(drho_ref=1e-3, trust0=1.0, release_tol=10.0, trust_decisions=10 ** 6), steps=50)
     _, released, delta, decisions = b.controller_state()
     assert released and delta == 0.0 and decisions == 50
     _, aux = b.controller_trace(50)
-    assert aux[0, 3] != 0.0 and np.all(aux[1:, 3] == 0.0)  # released from t >= 2
+    assert aux[0, 3] != 0.0 and np.all(aux[1:, 3] == 0.0)  # released once two periods are recorded
     b.set_controller(None)
     assert not b.controller_state()[0]
     b.step(10)
@@ -183,12 +195,13 @@ def test_release_returns_control_for_good():
 
 def test_no_progress_returns_control():
     # a constant network holds the inlet at a fixed density; once the outlet
-    # error stops falling by 10 % within stall_steps decisions, the plain
+    # error stops falling by 10 % within stall_decisions decisions, the plain
     # update takes over for good
     p = np.zeros(mo.N_PARAMS, np.float32)
     p[-1] = 0.5
     (fa, fb, ha, hb, b), net = _plain_and_controlled(
-        p, dict(drho_ref=2e-3, trust0=5.0, release_tol=1e-12, trust_steps=10 ** 6, stall_steps=40), steps=1500)
+        p, dict(drho_ref=2e-3, trust0=5.0, release_tol=1e-12, trust_decisions=10 ** 6, stall_decisions=40),
+        steps=1500)
     _, released, delta, decisions = b.controller_state()
     assert released and delta == 0.0
     _, aux = b.controller_trace(1500)
