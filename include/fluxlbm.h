@@ -219,7 +219,7 @@ flbm_status flbm_gemm_bf16(const float *A, int64_t a_rs, int64_t a_cs, const flo
 
 typedef struct flbm_controller_params {
     float geometry[15];   /* static inputs 0..14 of the network (sample and inlet-slice statistics) */
-    float reserved;
+    float margin;         /* >= 0: the proposal aims below the prediction, r - margin */
     double drho_ref;      /* reference inlet-outlet density difference (input 31, absolute proposal) */
     double gain;          /* fraction of the step from the plain density to the proposal taken */
     double trust0;        /* initial bound on |Q_in - Q*| / Q* that a proposal may cause */
@@ -244,7 +244,9 @@ typedef struct flbm_controller_params {
  * density difference drho_inf, either absolute (relative = 0: r =
  * log(drho_inf / drho_ref) clipped to [-4, 4], proposal rho_hat = rho_out +
  * drho_ref exp(r)) or as the remaining relative rise (relative = 1: r =
- * log(drho_inf / drho) clipped to [-2, 3], rho_hat = rho_out + drho exp(r)).
+ * log(drho_inf / drho) clipped to [-2, 3], rho_hat = rho_out + drho exp(r)),
+ * with r replaced by r - margin (an undershoot that leaves the last part of
+ * the rise to the plain update).
  * The proposal is held for the next period; every step in it uses
  *   rho_in = rho_plain + clip(gain (rho_hat - rho_plain), +-bound rho0 |Q*| / A)
  * with rho_plain the update of eq. potential of that step and bound = trust0

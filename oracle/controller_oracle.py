@@ -22,8 +22,9 @@ inputs x (32):
 network   y = net(x), computed by the network oracle with BF16 operands (the
           precision of the device's matrix products);
 proposal  absolute: r = clip(y, -4, 4) = log(drho_inf / drho_ref),
-          rho_hat = rho_out + drho_ref exp(r); relative: r = clip(y, -2, 3) =
-          log(drho_inf / drho), rho_hat = rho_out + drho exp(r);
+          rho_hat = rho_out + drho_ref exp(r - margin); relative: r =
+          clip(y, -2, 3) = log(drho_inf / drho), rho_hat = rho_out +
+          drho exp(r - margin) (margin >= 0 aims below the prediction);
 bound     b = trust0 max(0, 1 - n / trust_decisions) after n decisions,
           limit = b rho0 |Q*| / A_in;
 release   for good once |Qbar(P - 1) - Q*| / |Q*| <= release_tol (P >= 2), or
@@ -52,12 +53,13 @@ def _f32(v):
 
 class OracleController:
     def __init__(self, params, geometry, *, drho_ref, gain, trust0, release_tol, trust_decisions,
-                 relative=False, stall_decisions=0, period=1):
+                 relative=False, stall_decisions=0, period=1, margin=0.0):
         self.params = np.asarray(params, np.float64)
         self.geometry = np.asarray(geometry, np.float64)
         self.drho_ref, self.gain, self.trust0 = float(drho_ref), float(gain), float(trust0)
         self.release_tol, self.trust_decisions = float(release_tol), int(trust_decisions)
         self.relative, self.stall_decisions, self.period = bool(relative), int(stall_decisions), int(period)
+        self.margin = float(np.float32(margin))
         self.best, self.best_n = 0.0, 0
         self.qout = []      # Q_out of every step taken
         self.rho_in = []    # rho_in of every step taken
@@ -101,9 +103,9 @@ class OracleController:
         if self.relative:
             if not drho > 0.0:
                 return None
-            rho_hat = rho_out + drho * math.exp(min(3.0, max(-2.0, y)))
+            rho_hat = rho_out + drho * math.exp(min(3.0, max(-2.0, y)) - self.margin)
         else:
-            rho_hat = rho_out + self.drho_ref * math.exp(min(4.0, max(-4.0, y)))
+            rho_hat = rho_out + self.drho_ref * math.exp(min(4.0, max(-4.0, y)) - self.margin)
         if not math.isfinite(rho_hat):
             return None
         return rho_hat, limit

@@ -138,7 +138,8 @@ def make_sample(n: int, porosity: float, seed: int, *, tau: float, darcy: float,
 
 
 def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_margin=2000,
-        max_steps=400000, chunk=4096, record=False, settle_tol=None, settings=None, ref_scale=1.0):
+        max_steps=400000, chunk=4096, record=False, settle_tol=None, settings=None, ref_scale=1.0,
+        progress=None):
     """Run from rest until the two-step mean outlet error has stayed within
     ``settle_tol`` (default tol) for max(min_margin, margin_frac * t) steps.
 
@@ -164,7 +165,8 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
             lat.set_controller(net, geom, drho_ref=drho_ref, gain=s["gain"],
                                trust0=s["trust0"] if active else 0.0, release_tol=s["release_tol"],
                                trust_decisions=int(s["trust_decisions"]), relative=bool(s["relative"]),
-                               stall_decisions=int(s["stall_decisions"]), period=period)
+                               stall_decisions=int(s["stall_decisions"]), period=period,
+                               margin=float(s.get("margin", 0.0)))
         q = kw["q_target"]
         hist, xs, auxs = [], [], []
         seen = 0
@@ -183,6 +185,10 @@ def run(mask, kw, *, net=None, active=False, tol=1e-3, margin_frac=0.25, min_mar
                     seen = decisions
             qo = np.concatenate([hh[:, 2] for hh in hist])
             st = steps_to_tol(qo, q, settle_tol)
+            if progress and len(hist) % 8 == 0:
+                e = two_step_error(qo[-2:], q)[0]
+                progress(f"  {'learned' if active else 'plain'}: step {lat.step_count}, "
+                         f"|Q_out - Q*|/Q* {e:.2e}, {time.perf_counter() - t0:.0f} s")
             if st is not None and lat.step_count - st >= max(min_margin, margin_frac * st):
                 break
         secs = time.perf_counter() - t0
@@ -372,18 +378,19 @@ def load_weights(path: str = DEFAULT_WEIGHTS):
 
 def settings_of(meta) -> dict:
     """The controller settings the weights were trained with."""
-    keep = ("relative", "gain", "trust0", "release_tol", "trust_decisions", "stall_decisions")
+    keep = ("relative", "gain", "trust0", "release_tol", "trust_decisions", "stall_decisions", "margin")
     return {k: v for k, v in meta.get("settings", {}).items() if k in keep}
 
 
-def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000):
+def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000, progress=None):
     """Steps to tol for the plain update and for the learned controller on
     the same sample and GPU."""
     net = fluxlbm.Mlp(16)
     net.set_params(params)
     try:
-        plain = run(mask, kw, tol=tol, max_steps=max_steps)
-        learned = run(mask, kw, net=net, active=True, tol=tol, max_steps=max_steps, settings=settings)
+        plain = run(mask, kw, tol=tol, max_steps=max_steps, progress=progress)
+        learned = run(mask, kw, net=net, active=True, tol=tol, max_steps=max_steps, settings=settings,
+                      progress=progress)
     finally:
         net.close()
     out = dict(plain_steps=plain["steps_to_tol"], learned_steps=learned["steps_to_tol"],
@@ -415,6 +422,8 @@ def main(argv=None):
     e.add_argument("--darcy", type=float, default=1e-5)
     e.add_argument("--trust0", type=float, default=None)
     e.add_argument("--release-tol", type=float, default=None)
+    e.add_argument("--max-steps", type=int, default=1000000)
+    e.add_argument("--margin", type=float, default=None)
     a = ap.parse_args(argv)
     if a.cmd == "train":
         meta = train(a.out, samples=a.samples, dagger_rounds=a.dagger, steps=a.steps, seed=a.seed,
@@ -428,10 +437,14 @@ def main(argv=None):
             settings["trust0"] = a.trust0
         if a.release_tol is not None:
             settings["release_tol"] = a.release_tol
+        if a.margin is not None:
+            settings["margin"] = a.margin
         for n in a.n:
             for sd in a.seed:
                 mask, kw = make_sample(n, a.porosity, sd, tau=a.tau, darcy=a.darcy)
-                r = evaluate(params, mask, kw, settings=settings)
+                print(f"sample n={n} seed={sd}: {int((mask == 0).sum())} pore voxels", flush=True)
+                r = evaluate(params, mask, kw, settings=settings, max_steps=a.max_steps,
+                             progress=lambda m: print(m, flush=True))
                 print(json.dumps(dict(n=n, seed=sd, porosity=a.porosity, tau=a.tau, darcy=a.darcy, **r)),
                       flush=True)
 

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
     R drho, ux, uy, uz;
     if (collide) {
         mrt_collide<true>(g, snu, (R)a.rho0, (R)a.inv_rho0, (R)c.alpha, gx, gy, gz, drho, ux, uy, uz);
+        conserve_mass<T>(g, drho, (uint32_t)s);
     } else {
         drho = ux = uy = uz = 0;
 #pragma unroll
@@ -184,12 +185,13 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
 #pragma unroll
         for (int q = 0; q < 19; ++q) {
             const uint32_t cc = (uint32_t)(cw >> (2 * q)) & 3u;
-            if (cc) s_next += (double)cc * (double)Codec<T>::dec(Codec<T>::enc(g[q], q), q);
+            if (cc) s_next += (double)cc * (double)Codec<T>::dec(Codec<T>::enc(g[q], q, (uint32_t)s), q);
         }
     }
 
 #pragma unroll
-    for (int q = 0; q < 19; ++q) __builtin_nontemporal_store(Codec<T>::enc(g[q], q), &fout[(int64_t)q * npad + s]);
+    for (int q = 0; q < 19; ++q)
+        __builtin_nontemporal_store(Codec<T>::enc(g[q], q, (uint32_t)s), &fout[(int64_t)q * npad + s]);
 
     // recolouring: full relaxation of A and B to
     //   w_q N_A [1 + 9/2 u.xi_q + beta N_B n.xi_q],  w_q N_B [1 + 9/2 u.xi_q - beta N_A n.xi_q]

@@ -398,7 +398,7 @@ struct CtrlArgs {
     int32_t period;
     const float *params;
     const float *geometry;
-    double rho0, a_in, drho_ref, gain, trust0, release_tol;
+    double rho0, a_in, drho_ref, gain, trust0, release_tol, margin;
 };
 
 __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
         const double limit = bound * c.rho0 * qn / c.a_in;
         const double rho_plain = 1.0 + inlet_drho_plain(st, c.rd_next, c.rho0, (int64_t)c.a_in);
         const double r = c.relative ? fmin(3.0, fmax(-2.0, (double)y)) : fmin(4.0, fmax(-4.0, (double)y));
-        const double rho_hat = 1.0 + st->drho_out + (c.relative ? drho : c.drho_ref) * exp(r);
+        const double rho_hat = 1.0 + st->drho_out + (c.relative ? drho : c.drho_ref) * exp(r - c.margin);
         // a non-finite output is dropped before clipping (fmin/fmax would
         // turn a NaN into a bound)
         const bool on = isfinite(y) && isfinite(rho_hat) && qs > 0.0 && !st->ctrl_released &&
@@ -505,6 +505,7 @@ void launch_controller(flbm_ctx *c, hipStream_t s, int rd_next)
     a.gain = c->ctrl.gain;
     a.trust0 = c->ctrl.trust0;
     a.release_tol = c->ctrl.release_tol;
+    a.margin = c->ctrl.margin;
     hipLaunchKernelGGL(k_controller, dim3(1), dim3(256), 0, s, a);
 }
 
@@ -792,7 +793,8 @@ flbm_status flbm_set_controller(flbm_ctx *c, const flbm_mlp *net, const flbm_con
     if (net) {
         if (!(p->trust0 >= 0.0) || !std::isfinite(p->gain) || p->trust_decisions < 0 || !(p->release_tol >= 0.0) ||
             !(p->drho_ref > 0.0) || !std::isfinite(p->drho_ref) || p->stall_decisions < 0 ||
-            (p->relative != 0 && p->relative != 1) || p->period < 1)
+            (p->relative != 0 && p->relative != 1) || p->period < 1 || !(p->margin >= 0.0f) ||
+            !std::isfinite(p->margin))
             return fail(c, FLBM_EINVAL, "bad controller parameters");
         c->ctrl = *p;
         c->ctrl_net = net;

@@ -44,7 +44,7 @@ class FlbmError(RuntimeError):
 
 class flbm_controller_params(ctypes.Structure):
     _fields_ = [
-        ("geometry", ctypes.c_float * 15), ("reserved", ctypes.c_float),
+        ("geometry", ctypes.c_float * 15), ("margin", ctypes.c_float),
         ("drho_ref", ctypes.c_double), ("gain", ctypes.c_double), ("trust0", ctypes.c_double), ("release_tol", ctypes.c_double),
         ("trust_decisions", ctypes.c_int32), ("relative", ctypes.c_int32),
         ("stall_decisions", ctypes.c_int32), ("period", ctypes.c_int32),
@@ -704,7 +704,8 @@ class Lattice:
         return flbm_device_layout(self.ctx)
 
     def set_controller(self, net: "Mlp | None", geometry=None, *, drho_ref=1e-3, gain=1.0, trust0=0.5,
-                       release_tol=1e-3, trust_decisions=20000, relative=False, stall_decisions=0, period=1):
+                       release_tol=1e-3, trust_decisions=20000, relative=False, stall_decisions=0, period=1,
+                       margin=0.0):
         if net is None:
             flbm_set_controller(self.ctx, None, None)
             self._ctrl_net = None
@@ -717,6 +718,7 @@ class Lattice:
             p.geometry[i] = float(g[i])
         p.drho_ref = float(drho_ref)
         p.relative, p.stall_decisions, p.period = int(bool(relative)), int(stall_decisions), int(period)
+        p.margin = float(margin)
         p.gain, p.trust0, p.release_tol = float(gain), float(trust0), float(release_tol)
         p.trust_decisions = int(trust_decisions)
         flbm_set_controller(self.ctx, net.handle, p)

@@ -228,3 +228,30 @@ def test_fp16dev_slit_channel_against_oracle():
     assert np.abs(h[:, 1] - 0.5).max() <= 1e-12
     q_err = abs(0.5 * (h[-1, 2] + h[-2, 2]) - 0.5 * (h_orc[-1, 2] + h_orc[-2, 2])) / 0.5
     assert q_err <= 1e-2, f"outlet flux error {q_err:.3e}"
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-4), ("fp16dev", 1e-2)])
+def test_steady_flux_and_permeability_match_fp64(precision, tol):
+    """A long pack (140 planes) run for 120,000 steps (well into the approach
+    to steady state) against the same run in FP64: the outlet flux and the
+    inlet-outlet density difference (the permeability's denominator) agree
+    to 1e-4 relative in FP32 (1e-2 for FP16 deviations, whose 11-bit
+    significands carry the velocity on top of a much larger density
+    deviation). Reduced-precision rounding must not create mass: a coherent
+    per-site source would add up along the planes into a flux error (1.3e-3
+    over the 268 planes of a 256^3 pack before the rest population was made
+    mass-exact)."""
+    mask, _, _ = inputs.sphere_pack((140, 32, 32), 0.45, 17, reservoir_layers=6)
+    q = 1e-5 * 32 * 32
+    runs = {}
+    for prec in ("fp64", precision):
+        lat = fluxlbm.Lattice(mask, precision=prec, tau=0.7, q_target=q, watchdog_every=4096)
+        lat.init_equilibrium()
+        lat.step(120000)
+        h = lat.history(2048)
+        runs[prec] = (0.5 * (h[-1, 2] + h[-2, 2]), h[:, 0].mean() - 1.0)
+        lat.close()
+    (q64, d64), (qp, dp) = runs["fp64"], runs[precision]
+    assert abs(q64 - q) <= 0.1 * q                  # FP64 is well into the approach
+    assert abs(qp - q64) <= tol * q, (qp / q - 1, q64 / q - 1)
+    assert abs(dp - d64) <= tol * d64, (dp / d64 - 1)
