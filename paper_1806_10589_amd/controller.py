@@ -382,22 +382,26 @@ def settings_of(meta) -> dict:
     return {k: v for k, v in meta.get("settings", {}).items() if k in keep}
 
 
-def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000, progress=None):
+def evaluate(params, mask, kw, *, tol=1e-3, settings=None, max_steps=2000000, progress=None,
+             which=("plain", "learned"), margin_frac=0.25):
     """Steps to tol for the plain update and for the learned controller on
-    the same sample and GPU."""
-    net = fluxlbm.Mlp(16)
-    net.set_params(params)
-    try:
-        plain = run(mask, kw, tol=tol, max_steps=max_steps, progress=progress)
-        learned = run(mask, kw, net=net, active=True, tol=tol, max_steps=max_steps, settings=settings,
-                      progress=progress)
-    finally:
-        net.close()
-    out = dict(plain_steps=plain["steps_to_tol"], learned_steps=learned["steps_to_tol"],
-               plain_secs=plain["secs"], learned_secs=learned["secs"],
-               controller=learned.get("controller"))
-    if plain["steps_to_tol"] and learned["steps_to_tol"]:
-        out["gain"] = plain["steps_to_tol"] / learned["steps_to_tol"]
+    the same sample and GPU (``which`` picks one or both)."""
+    out = {}
+    if "plain" in which:
+        plain = run(mask, kw, tol=tol, max_steps=max_steps, progress=progress, margin_frac=margin_frac)
+        out.update(plain_steps=plain["steps_to_tol"], plain_secs=plain["secs"])
+    if "learned" in which:
+        net = fluxlbm.Mlp(16)
+        net.set_params(params)
+        try:
+            learned = run(mask, kw, net=net, active=True, tol=tol, max_steps=max_steps, settings=settings,
+                          progress=progress, margin_frac=margin_frac)
+        finally:
+            net.close()
+        out.update(learned_steps=learned["steps_to_tol"], learned_secs=learned["secs"],
+                   controller=learned.get("controller"), period=learned["period"])
+    if out.get("plain_steps") and out.get("learned_steps"):
+        out["gain"] = out["plain_steps"] / out["learned_steps"]
     return out
 
 
@@ -424,6 +428,9 @@ def main(argv=None):
     e.add_argument("--release-tol", type=float, default=None)
     e.add_argument("--max-steps", type=int, default=1000000)
     e.add_argument("--margin", type=float, default=None)
+    e.add_argument("--only", choices=["plain", "learned"], default=None)
+    e.add_argument("--margin-frac", type=float, default=0.25,
+                   help="steps after settling, as a fraction of the settling time, that must stay within tol")
     a = ap.parse_args(argv)
     if a.cmd == "train":
         meta = train(a.out, samples=a.samples, dagger_rounds=a.dagger, steps=a.steps, seed=a.seed,
@@ -444,7 +451,8 @@ def main(argv=None):
                 mask, kw = make_sample(n, a.porosity, sd, tau=a.tau, darcy=a.darcy)
                 print(f"sample n={n} seed={sd}: {int((mask == 0).sum())} pore voxels", flush=True)
                 r = evaluate(params, mask, kw, settings=settings, max_steps=a.max_steps,
-                             progress=lambda m: print(m, flush=True))
+                             progress=lambda m: print(m, flush=True),
+                             which=(a.only,) if a.only else ("plain", "learned"), margin_frac=a.margin_frac)
                 print(json.dumps(dict(n=n, seed=sd, porosity=a.porosity, tau=a.tau, darcy=a.darcy, **r)),
                       flush=True)
 
