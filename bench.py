@@ -30,7 +30,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in ("kernels.h", "engine.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in ("kernels.h", "engine.hip", "pull_format.h")]
 
 CONFIGS = {
     # name: (builder, lattice kwargs, description)
@@ -50,17 +50,39 @@ CONFIGS = {
 SCHEDULE_CACHE = os.path.join(ROOT, "paper_1806_10589_amd", "schedule_cache.txt")
 
 
-def bytes_per_lup(precision: str, model: str = "bgk") -> int:
+def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share16: float = 0.0) -> float:
     """Algorithmic bytes of one pore-site update: 19 populations read and
-    written once in the storage type, plus 18 int32 pull indices. The colour
-    model adds, per site, the phase pass (14 D3Q7 colour values read, 6
-    indices, N_A, N_B and phi written) and, in the colour step, phi of the 18
-    neighbours, N_A, N_B and the 14 recoloured values written."""
+    written once in the storage type, plus the pull table: 18 int32 indices,
+    or, on the shares of tiles that read compact codes, 18 8-bit or 16-bit
+    codes and the tile's 80-byte header over its 512 sites. The colour model
+    (int32 table) adds, per site, the phase pass (14 D3Q7 colour values
+    read, 6 indices, N_A, N_B and phi written) and, in the colour step, phi
+    of the 18 neighbours, N_A, N_B and the 14 recoloured values written."""
     elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
-    single = 19 * 2 * elem + 18 * 4
+    hdr = 80 / 512
+    table = 18 * 4 * (1.0 - share8 - share16) + (18 + hdr) * share8 + (36 + hdr) * share16
+    single = 19 * 2 * elem + table
     if model != "colour":
         return single
     return single + (14 * elem + 6 * 4 + 3 * elem) + (18 * elem + 2 * elem + 14 * elem)
+
+
+def pull_share(lats, fmt: str):
+    """Set the pull-table format of the lattices; return the shares of their
+    tiles that read 8-bit and 16-bit codes."""
+    from paper_1806_10589_amd import fluxlbm
+
+    code = {"compact": fluxlbm.FLBM_PULL_COMPACT, "half": fluxlbm.FLBM_PULL_HALF,
+            "int32": fluxlbm.FLBM_PULL_INT32}[fmt]
+    t8 = t16 = tiles = 0
+    for lat in lats:
+        if lat.pull_format()[0] != code:
+            lat.set_pull_format(code)
+        _, a, b, t = lat.pull_format()
+        t8 += a
+        t16 += b
+        tiles += t
+    return (t8 / tiles, t16 / tiles) if tiles else (0.0, 0.0)
 
 
 def kernel_source_hash() -> str:
@@ -143,6 +165,7 @@ def run_batch(args, cfg):
           file=sys.stderr, flush=True)
     lats = [fluxlbm.Lattice(m, watchdog_every=1000, **kw) for m, kw, _ in samples]
     n_total = sum(l.n_sites for l in lats)
+    share = pull_share(lats, args.pull)
     b = fluxlbm.Batch(lats)
     sched, ms_tuned = b.autotune(SCHEDULE_CACHE if os.access(os.path.dirname(SCHEDULE_CACHE), os.W_OK) else None,
                                  trial_steps=3)
@@ -173,7 +196,7 @@ def run_batch(args, cfg):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_seq = e0.elapsed_time(e1) / k_seq
-    bpl = bytes_per_lup(cfg["precision"])
+    bpl = bytes_per_lup(cfg["precision"], "bgk", *share)
     achieved = n_total * bpl / (ms_kernel * 1e-3) / 1e9
     out = {
         "metric": "MLUPS (pore sites) + HBM GB/s; steps-to-flux-tol, learned vs plain",
@@ -196,6 +219,8 @@ def run_batch(args, cfg):
             "tau": cfg["tau"],
             "precision": cfg["precision"],
             "schedule": sched,
+            "pull_table": args.pull,
+            "tile_share_8bit_16bit": [round(v, 4) for v in share],
         },
         "status": "ok" if rc == fluxlbm.FLBM_OK else f"unstable (sample {bad})",
         "sequential_ms_per_step": round(ms_seq, 5),
@@ -208,7 +233,7 @@ def run_batch(args, cfg):
             "traffic": None,
             "kernel": "k_batch_step",
             "kernel_ms": round(ms_kernel, 5),
-            "bytes_per_lup": bpl,
+            "bytes_per_lup": round(bpl, 2),
         },
     }
     m0, kw0, _ = samples[0]
@@ -310,6 +335,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-controller", action="store_true")
+    ap.add_argument("--pull", choices=["compact", "half", "int32"], default="compact",
+                    help="pull-table format of the single-fluid step: 8/16-bit codes, 16-bit codes, or the "
+                         "int32 table (colour: int32 always)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -328,6 +356,7 @@ def main():
     print(f"[bench] workload {args.config}: mask {mask.shape}, pore sites {(mask == 0).sum()}",
           file=sys.stderr, flush=True)
     lat = fluxlbm.Lattice(mask, watchdog_every=1000, **kw)
+    share = pull_share([lat], args.pull) if kw.get("model") != "colour" else (0.0, 0.0)
     if kw.get("model") == "colour":
         z = lat.coords()[:, 2]
         na = (z < cfg["reservoir"]).astype(float)
@@ -358,7 +387,7 @@ def main():
 
     # per-kernel durations with HIP events on the launch stream
     ms_plane, ms_kernel = lat.profile_kernels(args.profile_steps)
-    bpl = bytes_per_lup(kw["precision"], kw.get("model", "bgk"))
+    bpl = bytes_per_lup(kw["precision"], kw.get("model", "bgk"), *share)
     achieved = n * bpl / (ms_kernel * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
@@ -370,7 +399,7 @@ def main():
         "kernel": "k_phase+k_colour" if kw.get("model") == "colour" else "k_stream_collide",
         "kernel_ms": round(ms_kernel, 5),
         "plane_kernel_ms": round(ms_plane, 5),
-        "bytes_per_lup": bpl,
+        "bytes_per_lup": round(bpl, 2),
     }
     out = {
         "metric": "MLUPS (pore sites) + HBM GB/s; steps-to-flux-tol, learned vs plain",
@@ -394,6 +423,8 @@ def main():
             "q_target": kw["q_target"],
             "precision": kw["precision"],
             "collision": kw.get("model", "bgk"),
+            "pull_table": "int32" if kw.get("model") == "colour" else args.pull,
+            "tile_share_8bit_16bit": [round(v, 4) for v in share],
             **info,
         },
         "hbm_gbs_model": round(mlups * bpl / 1e3, 1),

@@ -357,6 +357,48 @@ flbm_status flbm_read_phase(flbm_ctx *c, double *phi);
  * Methods, before eq. inlet). Host-only; needs no device. */
 flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
 
+/* Pull-table format of the single-fluid step (Methods: streaming pulls each
+ * population from the site x - xi_q; the table only says where that value
+ * is stored). Every format addresses the same slots, so results are bitwise
+ * equal; they differ in the bytes a step reads per site.
+ *   FLBM_PULL_INT32    the int32 table above: 72 bytes per site.
+ *   FLBM_PULL_HALF     per tile of 512 consecutive sites one int32 base per
+ *                      direction, per site 16-bit codes, two to a word:
+ *                      code c <= 0xFFFD is the flat index base + c, 0xFFFE
+ *                      the boundary-unknown sentinel, 0xFFFF the bounce-back
+ *                      slot opp(q)*n_pad + site: 36 bytes per site.
+ *   FLBM_PULL_COMPACT  (the default where available) as HALF, but a tile
+ *                      whose sources fit takes 8-bit codes against the
+ *                      site's position p in the tile: c <= 0xFD is base +
+ *                      p + c, 0xFE the sentinel, 0xFF bounce-back: 18 bytes
+ *                      per site.
+ * A tile whose sources of some direction span more than a form's range
+ * falls back to the next wider form, down to the int32 table. The colour
+ * model, and lattices too large for the 4 GiB buffer path, have no compact
+ * table (FLBM_ESTATE for the coded formats). limit16 (<= 0xFFFD) and limit8
+ * (<= 0xFD) below the defaults (0 means the default) are a testing aid that
+ * sends more tiles to the wider forms. Synchronises; rebuilds the codes on
+ * the host (O(18 n)) when a limit changes. */
+#define FLBM_PULL_INT32 0
+#define FLBM_PULL_HALF 1
+#define FLBM_PULL_COMPACT 2
+flbm_status flbm_set_pull_format(flbm_ctx *c, int32_t format, int32_t limit16, int32_t limit8);
+/* The format in use and, of the `tiles` tiles, how many read 8-bit and
+ * 16-bit codes (the rest read the int32 table; both 0 for FLBM_PULL_INT32).
+ * Host-only. */
+flbm_status flbm_pull_format_info(const flbm_ctx *c, int32_t *format, int64_t *tiles8, int64_t *tiles16,
+                                  int64_t *tiles);
+/* Host copy of the compact table: 16-bit codes uint32 [9][n_pad] (word k:
+ * direction 2k+1 in bits 0-15, 2k+2 in bits 16-31), 8-bit codes uint32
+ * [4][n_pad] (byte j of word k: direction 4k+j+1) and uint16 [n_pad]
+ * (directions 17 in bits 0-7, 18 in bits 8-15), and the header int32
+ * [tiles][20] (entries 0..17: the base of direction q at q-1; entry 18 the
+ * tile's form: 0 int32 table, 1 16-bit, 2 8-bit; entry 19: 0). A tile's
+ * rows in the forms it does not use are zero. Any pointer may be NULL.
+ * Host-only; FLBM_ESTATE without a compact table. */
+flbm_status flbm_get_compact_pull(const flbm_ctx *c, uint32_t *codes16, uint32_t *codes8, uint16_t *codes8_tail,
+                                  int32_t *hdr);
+
 /* Raw checkpoint of the stored state: flbm_state_bytes gives the size; save
  * copies the current distribution buffers (storage precision: f as
  * deviations, then A and B for the colour model), the step count and the

@@ -67,6 +67,11 @@ struct flbm_ctx {
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
     int32_t *nbr = nullptr;
+    // compact pull table (single-fluid model on the buffer path)
+    CompactPull pull;
+    int pull_format = FLBM_PULL_INT32;
+    uint32_t *pull_codes = nullptr, *pull_bytes = nullptr;
+    int32_t *pull_hdr = nullptr;
     DevState *st = nullptr;
     double *kpart = nullptr, *bpart_in = nullptr, *bpart_out = nullptr, *spart = nullptr;
     uint64_t *kcoef = nullptr;
@@ -139,6 +144,25 @@ template <> _Float16 host_enc<_Float16>(double g, int q)
     return (_Float16)(float)(g * (double)(1u << d3q19::half_shift(q)));
 }
 
+// byte codes: [4][n_pad] words, then the [n_pad] 16-bit row
+size_t pull_bytes_size(const flbm_ctx *c)
+{
+    return c->pull.bytes.size() * sizeof(uint32_t) + c->pull.tail.size() * sizeof(uint16_t);
+}
+
+flbm_status upload_pull(flbm_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->pull_codes, c->pull.codes.data(), c->pull.codes.size() * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pull_bytes, c->pull.bytes.data(), c->pull.bytes.size() * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((char *)c->pull_bytes + c->pull.bytes.size() * sizeof(uint32_t), c->pull.tail.data(),
+                             c->pull.tail.size() * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pull_hdr, c->pull.hdr.data(), c->pull.hdr.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    return FLBM_OK;
+}
+
 size_t f_bytes(const flbm_ctx *c) { return (size_t)(19 * c->lat.n_pad + SENT_PAD) * c->elem; }
 
 // Carve the device slab. With base == nullptr only the size is computed.
@@ -154,6 +178,9 @@ size_t carve(flbm_ctx *c, char *base)
     char *f0 = take(f_bytes(c));
     char *f1 = take(f_bytes(c));
     char *nb = take((size_t)18 * npad * sizeof(int32_t));
+    char *pcw = c->pull.tiles ? take(c->pull.codes.size() * sizeof(uint32_t)) : nullptr;
+    char *pcb = c->pull.tiles ? take(pull_bytes_size(c)) : nullptr;
+    char *pch = c->pull.tiles ? take(c->pull.hdr.size() * sizeof(int32_t)) : nullptr;
     char *st = take(sizeof(DevState));
     char *kp = take(PLANE_MAX_BLOCKS * sizeof(double));
     char *bi = take((size_t)std::max(1, c->nt_in) * sizeof(double));
@@ -180,6 +207,9 @@ size_t carve(flbm_ctx *c, char *base)
         c->f[0] = f0;
         c->f[1] = f1;
         c->nbr = (int32_t *)nb;
+        c->pull_codes = (uint32_t *)pcw;
+        c->pull_bytes = (uint32_t *)pcb;
+        c->pull_hdr = (int32_t *)pch;
         c->st = (DevState *)st;
         c->kpart = (double *)kp;
         c->bpart_in = (double *)bi;
@@ -227,6 +257,12 @@ StepArgs step_args(const flbm_ctx *c)
     a.tout0 = flux ? c->tout0 : c->tiles;
     a.n_bnd = c->n_bnd;
     a.hist_cap = HIST_CAP;
+    const bool compact = c->pull_format != FLBM_PULL_INT32 && c->use_buf && c->pull.tiles > 0;
+    a.pull_codes = compact ? c->pull_codes : nullptr;
+    a.pull_bytes = compact ? c->pull_bytes : nullptr;
+    a.pull_hdr = compact ? c->pull_hdr : nullptr;
+    a.codes_bytes = compact ? (uint32_t)(c->pull.codes.size() * sizeof(uint32_t)) : 0u;
+    a.bytes_bytes = compact ? (uint32_t)pull_bytes_size(c) : 0u;
     a.flux_mode = flux;
     a.rho0 = c->p.rho0;
     a.inv_rho0 = 1.0 / c->p.rho0;
@@ -601,6 +637,10 @@ flbm_status setup_device(flbm_ctx *c, void *mem)
     carve(c, (char *)mem);
     HIPCHK(c, hipMemcpyAsync(c->nbr, c->lat.nbr.data(), c->lat.nbr.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
+    if (c->pull.tiles) {
+        flbm_status rc = upload_pull(c);
+        if (rc) return rc;
+    }
     if (!c->lat.kcoef.empty())
         HIPCHK(c, hipMemcpyAsync(c->kcoef, c->lat.kcoef.data(), c->lat.kcoef.size() * sizeof(uint64_t),
                                  hipMemcpyHostToDevice, c->stream));
@@ -709,6 +749,20 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
     }
     c->tiles = (int)(c->lat.n_pad / TILE);
     c->use_buf = f_bytes(c) < (1ull << 32) && (uint64_t)18 * c->lat.n_pad * 4 < (1ull << 32);
+    if (!c->colour && c->use_buf) {
+        // the single-fluid step reads the compact pull table where it fits
+        e = build_compact_pull(c->lat, TILE, (int32_t)PULL_MAX_CODE, (int32_t)PULL_MAX_BYTE, c->pull);
+        if (!e.empty()) {
+            delete c;
+            return FLBM_ENOMEM;
+        }
+        e = check_compact_pull(c->lat, c->pull);
+        if (!e.empty()) {
+            delete c;
+            return FLBM_EINVAL;
+        }
+        c->pull_format = FLBM_PULL_COMPACT;
+    }
     c->blocks256 = (int)(c->lat.n_pad / BLOCK);
     c->obs_slots = std::max(c->tiles, c->blocks256);
     const bool flux = p->z_mode == FLBM_Z_FLUX;
@@ -881,6 +935,61 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr)
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
     for (int q = 0; q < 18; ++q)
         std::memcpy(nbr + q * n, c->lat.nbr.data() + q * npad, n * sizeof(int32_t));
+    return FLBM_OK;
+}
+
+flbm_status flbm_set_pull_format(flbm_ctx *c, int32_t format, int32_t limit16, int32_t limit8)
+{
+    if (!c) return FLBM_EINVAL;
+    if (format != FLBM_PULL_INT32 && format != FLBM_PULL_HALF && format != FLBM_PULL_COMPACT)
+        return fail(c, FLBM_EINVAL, "unknown pull format");
+    if (limit16 < 0 || (uint32_t)limit16 > PULL_MAX_CODE || limit8 < 0 || (uint32_t)limit8 > PULL_MAX_BYTE)
+        return fail(c, FLBM_EINVAL, "code limit out of range");
+    if (format != FLBM_PULL_INT32 && !c->pull.tiles)
+        return fail(c, FLBM_ESTATE, "no compact pull table (colour model, or a lattice past the 4 GiB buffer path)");
+    const int32_t l16 = limit16 ? limit16 : (int32_t)PULL_MAX_CODE;
+    const int32_t l8 = format == FLBM_PULL_COMPACT ? (limit8 ? limit8 : (int32_t)PULL_MAX_BYTE) : 0;
+    if (c->ready) {
+        HIPCHK(c, hipSetDevice(c->device));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    drop_graphs(c);
+    if (format != FLBM_PULL_INT32 && (l16 != c->pull.limit16 || l8 != c->pull.limit8)) {
+        std::string e = build_compact_pull(c->lat, TILE, l16, l8, c->pull);
+        if (!e.empty()) return fail(c, FLBM_ENOMEM, e);
+        e = check_compact_pull(c->lat, c->pull);
+        if (!e.empty()) return fail(c, FLBM_EINVAL, e);
+        if (c->ready) {
+            flbm_status rc = upload_pull(c);
+            if (rc) return rc;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    c->pull_format = format;
+    return FLBM_OK;
+}
+
+flbm_status flbm_pull_format_info(const flbm_ctx *c, int32_t *format, int64_t *tiles8, int64_t *tiles16,
+                                  int64_t *tiles)
+{
+    if (!c) return FLBM_EINVAL;
+    const bool on = c->pull_format != FLBM_PULL_INT32 && c->pull.tiles > 0;
+    if (format) *format = on ? c->pull_format : FLBM_PULL_INT32;
+    if (tiles8) *tiles8 = on ? c->pull.tiles8 : 0;
+    if (tiles16) *tiles16 = on ? c->pull.tiles16 : 0;
+    if (tiles) *tiles = c->tiles;
+    return FLBM_OK;
+}
+
+flbm_status flbm_get_compact_pull(const flbm_ctx *c, uint32_t *codes16, uint32_t *codes8, uint16_t *codes8_tail,
+                                  int32_t *hdr)
+{
+    if (!c) return FLBM_EINVAL;
+    if (!c->pull.tiles) return fail(const_cast<flbm_ctx *>(c), FLBM_ESTATE, "no compact pull table");
+    if (codes16) std::memcpy(codes16, c->pull.codes.data(), c->pull.codes.size() * sizeof(uint32_t));
+    if (codes8) std::memcpy(codes8, c->pull.bytes.data(), c->pull.bytes.size() * sizeof(uint32_t));
+    if (codes8_tail) std::memcpy(codes8_tail, c->pull.tail.data(), c->pull.tail.size() * sizeof(uint16_t));
+    if (hdr) std::memcpy(hdr, c->pull.hdr.data(), c->pull.hdr.size() * sizeof(int32_t));
     return FLBM_OK;
 }
 

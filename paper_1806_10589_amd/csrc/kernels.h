@@ -15,6 +15,7 @@
 
 #include "d3q19.h"
 #include "mrt.h"
+#include "pull_format.h"
 
 namespace flbm {
 
@@ -128,6 +129,10 @@ struct StepArgs {
     uint32_t *obs_bad;              // per-tile non-finite flag
     double *obs_na, *obs_nb;        // per-tile colour sums (two-fluid model)
     double *hist;
+    const uint32_t *pull_codes;     // compact pull table: 16-bit codes ([9][npad] words)
+    const uint32_t *pull_bytes;     // byte codes ([4][npad] words, then [npad] 16-bit)
+    const int32_t *pull_hdr;        // per-tile header ([tiles][PULL_HDR]); null: int32 table only
+    uint32_t codes_bytes, bytes_bytes;  // sizes of the two code arrays for the descriptors
 };
 
 struct PlaneArgs {
@@ -689,15 +694,70 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
 #pragma unroll
             for (int v = 0; v < V; ++v) g[v][0] = Codec<T>::dec(r[v], 0);
         }
+        const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
+        const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
+        const uint32_t sent = 19u * (uint32_t)npad;
+        // position of each of this thread's sites in the tile
+        const uint32_t p0 = (uint32_t)(s0 - (int64_t)tile * TILE);
+        if (form == PULL_TILE_BYTE) {
+            // byte codes: four words for directions 1..16, a 16-bit row for
+            // 17 and 18; flat index = base + position + code
+            const __amdgpu_buffer_rsrc_t rb = make_rsrc(a.pull_bytes, a.bytes_bytes);
+            uint32_t w[4][V];
+            uint16_t tl[V];
 #pragma unroll
-        for (int q = 1; q < 19; ++q) {
-            int32_t idx[V];
-            buf_load_v<V, int32_t, int32_t, SC_IDX_AUX>(rn, vi, (uint32_t)(q - 1) * (uint32_t)npad * 4u, idx);
+            for (int k = 0; k < 4; ++k)
+                buf_load_v<V, uint32_t, uint32_t, SC_IDX_AUX>(rb, vi, (uint32_t)k * (uint32_t)npad * 4u, w[k]);
+            buf_load_v<V, uint16_t, uint16_t, SC_IDX_AUX>(rb, (uint32_t)s0 * 2u, 16u * (uint32_t)npad, tl);
 #pragma unroll
-            for (int v = 0; v < V; ++v) {
-                T r[1];
-                buf_load_v<1, T, T>(rf, (uint32_t)idx[v] * (uint32_t)sizeof(T), 0u, r);
-                g[v][q] = Codec<T>::dec(r[0], q);
+            for (int q = 1; q < 19; ++q) {
+                const uint32_t base = (uint32_t)hdr[q - 1];
+                const uint32_t bb = (uint32_t)d3q19::opp(q) * (uint32_t)npad + (uint32_t)s0;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const uint32_t c = q <= 16 ? (w[(q - 1) >> 2][v] >> (((q - 1) & 3) * 8)) & 0xFFu
+                                               : ((uint32_t)tl[v] >> ((q - 17) * 8)) & 0xFFu;
+                    const uint32_t idx = c <= PULL_MAX_BYTE ? base + p0 + (uint32_t)v + c
+                                         : (c == PULL_BYTE_BOUNCE ? bb + (uint32_t)v : sent);
+                    T r[1];
+                    buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
+                    g[v][q] = Codec<T>::dec(r[0], q);
+                }
+            }
+        } else if (form == PULL_TILE_HALF) {
+            // 16-bit codes, two per word; flat index = base + code
+            const __amdgpu_buffer_rsrc_t rc = make_rsrc(a.pull_codes, a.codes_bytes);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                uint32_t w[V];
+                buf_load_v<V, uint32_t, uint32_t, SC_IDX_AUX>(rc, vi, (uint32_t)k * (uint32_t)npad * 4u, w);
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int q = 2 * k + 1 + half;
+                    const uint32_t base = (uint32_t)hdr[q - 1];
+                    const uint32_t bb = (uint32_t)d3q19::opp(q) * (uint32_t)npad + (uint32_t)s0;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const uint32_t c = half ? (w[v] >> 16) : (w[v] & 0xFFFFu);
+                        const uint32_t idx = c <= PULL_MAX_CODE ? base + c
+                                             : (c == PULL_BOUNCE ? bb + (uint32_t)v : sent);
+                        T r[1];
+                        buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
+                        g[v][q] = Codec<T>::dec(r[0], q);
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 1; q < 19; ++q) {
+                int32_t idx[V];
+                buf_load_v<V, int32_t, int32_t, SC_IDX_AUX>(rn, vi, (uint32_t)(q - 1) * (uint32_t)npad * 4u, idx);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    T r[1];
+                    buf_load_v<1, T, T>(rf, (uint32_t)idx[v] * (uint32_t)sizeof(T), 0u, r);
+                    g[v][q] = Codec<T>::dec(r[0], q);
+                }
             }
         }
     } else {

@@ -6,6 +6,7 @@
 
 #include "../../include/fluxlbm.h"
 #include "d3q19.h"
+#include "pull_format.h"
 
 namespace flbm {
 
@@ -165,6 +166,140 @@ std::string build_lattice(const uint8_t *solid_in, const LatticeSpec &spec, Latt
                     return "two inlet pulls read one population";
                 }
                 w |= (uint64_t)c << (2 * qq);
+            }
+        }
+    }
+    return std::string();
+}
+
+namespace {
+
+// Regular sources of direction q over the sites [s0, s0 + tile): the range
+// of (source - shift * position) over them; false if an entry is of no kind
+// the codes know.
+bool source_range(const Lattice &L, int q, int64_t s0, int tile, int shift, int64_t &lo, int64_t &hi)
+{
+    const int64_t npad = L.n_pad;
+    const int32_t *row = L.nbr.data() + (q - 1) * npad;
+    const int64_t reg = (int64_t)q * npad, bb = (int64_t)d3q19::opp(q) * npad;
+    lo = INT64_MAX;
+    hi = INT64_MIN;
+    for (int p = 0; p < tile; ++p) {
+        const int64_t s = s0 + p, e = row[s];
+        if (e == L.sentinel || e == bb + s) continue;
+        if (e < reg || e >= reg + npad) return false;
+        const int64_t v = e - shift * p;
+        lo = std::min(lo, v);
+        hi = std::max(hi, v);
+    }
+    if (lo > hi) lo = hi = reg;  // no regular source in this tile
+    return true;
+}
+
+uint32_t code_of(const Lattice &L, int q, int64_t s, int64_t base, int64_t p, int form)
+{
+    const int64_t e = L.nbr[(q - 1) * L.n_pad + s];
+    const bool bounce = e == (int64_t)d3q19::opp(q) * L.n_pad + s;
+    if (form == PULL_TILE_BYTE)
+        return e == L.sentinel ? PULL_BYTE_UNKNOWN : bounce ? PULL_BYTE_BOUNCE : (uint32_t)(e - base - p);
+    return e == L.sentinel ? PULL_UNKNOWN : bounce ? PULL_BOUNCE : (uint32_t)(e - base);
+}
+
+}  // namespace
+
+std::string build_compact_pull(const Lattice &L, int tile, int32_t limit16, int32_t limit8, CompactPull &cp)
+{
+    const int64_t npad = L.n_pad;
+    if (tile <= 0 || npad % tile != 0) return "tile does not divide the padded site count";
+    if (limit16 < 1 || (uint32_t)limit16 > PULL_MAX_CODE) return "16-bit code limit out of range";
+    if (limit8 < 0 || (uint32_t)limit8 > PULL_MAX_BYTE) return "byte code limit out of range";
+    cp.tile = tile;
+    cp.limit16 = limit16;
+    cp.limit8 = limit8;
+    cp.tiles = npad / tile;
+    try {
+        cp.codes.assign((size_t)9 * npad, 0u);
+        cp.bytes.assign((size_t)4 * npad, 0u);
+        cp.tail.assign((size_t)npad, 0);
+        cp.hdr.assign((size_t)cp.tiles * PULL_HDR, 0);
+    } catch (const std::bad_alloc &) {
+        return "host allocation failed while building the compact pull table";
+    }
+    parallel_for(0, cp.tiles, [&](int64_t t0, int64_t t1) {
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t s0 = t * tile;
+            int32_t *h = cp.hdr.data() + t * PULL_HDR;
+            int64_t base[19];
+            int form = limit8 > 0 ? PULL_TILE_BYTE : PULL_TILE_HALF;
+            for (; form > PULL_TILE_INT32; --form) {
+                const int shift = form == PULL_TILE_BYTE ? 1 : 0;
+                const int64_t lim = form == PULL_TILE_BYTE ? limit8 : limit16;
+                bool fits = true;
+                for (int q = 1; q < 19 && fits; ++q) {
+                    int64_t lo, hi;
+                    fits = source_range(L, q, s0, tile, shift, lo, hi) && hi - lo <= lim;
+                    base[q] = lo;
+                }
+                if (fits) break;
+            }
+            h[PULL_HDR_FORM] = form;
+            if (form == PULL_TILE_INT32) continue;
+            for (int q = 1; q < 19; ++q) {
+                h[q - 1] = (int32_t)base[q];
+                for (int64_t p = 0; p < tile; ++p) {
+                    const int64_t s = s0 + p;
+                    const uint32_t c = code_of(L, q, s, base[q], p, form);
+                    if (form == PULL_TILE_HALF) {
+                        cp.codes[(size_t)((q - 1) >> 1) * npad + s] |= c << (((q - 1) & 1) * 16);
+                    } else if (q <= 16) {
+                        cp.bytes[(size_t)((q - 1) >> 2) * npad + s] |= c << (((q - 1) & 3) * 8);
+                    } else {
+                        cp.tail[s] = (uint16_t)(cp.tail[s] | (c << ((q - 17) * 8)));
+                    }
+                }
+            }
+        }
+    });
+    cp.tiles16 = cp.tiles8 = 0;
+    for (int64_t t = 0; t < cp.tiles; ++t) {
+        const int f = cp.hdr[t * PULL_HDR + PULL_HDR_FORM];
+        cp.tiles16 += f == PULL_TILE_HALF;
+        cp.tiles8 += f == PULL_TILE_BYTE;
+    }
+    return std::string();
+}
+
+std::string check_compact_pull(const Lattice &L, const CompactPull &cp)
+{
+    const int64_t npad = L.n_pad;
+    if (cp.tile <= 0 || cp.tiles * cp.tile != npad) return "compact table of another lattice";
+    for (int64_t t = 0; t < cp.tiles; ++t) {
+        const int32_t *h = cp.hdr.data() + t * PULL_HDR;
+        const int form = h[PULL_HDR_FORM];
+        if (form < PULL_TILE_INT32 || form > PULL_TILE_BYTE || h[19] != 0) return "bad compact tile header";
+        for (int64_t p = 0; p < cp.tile; ++p) {
+            const int64_t s = t * cp.tile + p;
+            bool zero16 = true, zero8 = cp.tail[s] == 0;
+            for (int k = 0; k < 9; ++k) zero16 &= cp.codes[(size_t)k * npad + s] == 0;
+            for (int k = 0; k < 4; ++k) zero8 &= cp.bytes[(size_t)k * npad + s] == 0;
+            if ((form != PULL_TILE_HALF && !zero16) || (form != PULL_TILE_BYTE && !zero8))
+                return "codes outside the tile's form";
+            if (form == PULL_TILE_INT32) continue;
+            for (int q = 1; q < 19; ++q) {
+                int64_t e;
+                if (form == PULL_TILE_HALF) {
+                    const uint32_t c = (cp.codes[(size_t)((q - 1) >> 1) * npad + s] >> (((q - 1) & 1) * 16)) & 0xFFFFu;
+                    e = c == PULL_UNKNOWN ? L.sentinel
+                        : c == PULL_BOUNCE ? (int64_t)d3q19::opp(q) * npad + s
+                                           : (int64_t)h[q - 1] + c;
+                } else {
+                    const uint32_t c = q <= 16 ? (cp.bytes[(size_t)((q - 1) >> 2) * npad + s] >> (((q - 1) & 3) * 8)) & 0xFFu
+                                               : ((uint32_t)cp.tail[s] >> ((q - 17) * 8)) & 0xFFu;
+                    e = c == PULL_BYTE_UNKNOWN ? L.sentinel
+                        : c == PULL_BYTE_BOUNCE ? (int64_t)d3q19::opp(q) * npad + s
+                                                : (int64_t)h[q - 1] + p + c;
+                }
+                if (e != L.nbr[(size_t)(q - 1) * npad + s]) return "compact pull code decodes wrongly";
             }
         }
     }

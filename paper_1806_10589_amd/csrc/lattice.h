@@ -38,6 +38,30 @@ struct Lattice {
     std::vector<uint64_t> kcoef;  // [n01]
 };
 
+// Compact forms of the pull table (see pull_format.h) for tiles of `tile`
+// sites: 16-bit codes [9][n_pad], byte codes [4][n_pad] + [n_pad], and a
+// PULL_HDR-int32 header per tile. Rows of a tile in another form are zero.
+struct CompactPull {
+    int tile = 0;
+    int32_t limit16 = 0, limit8 = 0;  // largest regular code of each form (0: form not used)
+    int64_t tiles = 0, tiles16 = 0, tiles8 = 0;
+    std::vector<uint32_t> codes;   // [9][n_pad] 16-bit codes
+    std::vector<uint32_t> bytes;   // [4][n_pad] byte codes of directions 1..16
+    std::vector<uint16_t> tail;    // [n_pad] byte codes of directions 17 (low) and 18 (high)
+    std::vector<int32_t> hdr;      // [tiles][PULL_HDR]
+};
+
+// Builds the compact forms of L's pull table for tiles of `tile` sites
+// (n_pad must be a multiple): each tile takes byte codes if its sources fit
+// limit8 (0 <= limit8 <= PULL_MAX_BYTE; 0 turns byte codes off), else
+// 16-bit codes if they fit limit16 (1 <= limit16 <= PULL_MAX_CODE), else
+// the int32 table. Returns "" on success.
+std::string build_compact_pull(const Lattice &L, int tile, int32_t limit16, int32_t limit8, CompactPull &out);
+
+// Every entry of every coded tile decodes to the int32 table's entry, and
+// every row of a tile in another form is zero. Returns "" if it holds.
+std::string check_compact_pull(const Lattice &L, const CompactPull &cp);
+
 // Row length of every [q][site] array: a multiple of 1024 sites.
 int64_t padded_sites(int64_t n);
 

@@ -28,6 +28,8 @@ FLBM_ESTATE = -8
 FLBM_FP64, FLBM_FP32, FLBM_FP16DEV = 0, 1, 2
 FLBM_BGK, FLBM_COLOUR, FLBM_MRT = 0, 1, 2
 FLBM_Z_FLUX, FLBM_Z_PERIODIC, FLBM_Z_WALL = 0, 1, 2
+FLBM_PULL_INT32, FLBM_PULL_HALF, FLBM_PULL_COMPACT = 0, 1, 2
+PULL_HDR = 20  # int32 header entries per tile of the compact pull table
 
 PRECISIONS = {"fp64": FLBM_FP64, "fp32": FLBM_FP32, "fp16dev": FLBM_FP16DEV}
 MODELS = {"bgk": FLBM_BGK, "colour": FLBM_COLOUR, "mrt": FLBM_MRT}
@@ -105,6 +107,9 @@ _SIGS = {
     "flbm_write_colour": [_P, _P, _P],
     "flbm_read_phase": [_P, _P],
     "flbm_get_pull_table": [_P, _P],
+    "flbm_set_pull_format": [_P, _I32, _I32, _I32],
+    "flbm_pull_format_info": [_P, ctypes.POINTER(_I32), _I64P, _I64P, _I64P],
+    "flbm_get_compact_pull": [_P, _P, _P, _P, _P],
     "flbm_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "flbm_save_state": [_P, _P, ctypes.c_size_t],
     "flbm_load_state": [_P, _P, ctypes.c_size_t],
@@ -317,6 +322,32 @@ def flbm_get_pull_table(ctx, n_sites: int) -> np.ndarray:
     out = np.empty((18, n_sites), np.int32)
     _check(load_library().flbm_get_pull_table(ctx, out.ctypes.data), "flbm_get_pull_table", ctx)
     return out
+
+
+def flbm_set_pull_format(ctx, fmt: int, limit16: int = 0, limit8: int = 0) -> None:
+    _check(load_library().flbm_set_pull_format(ctx, int(fmt), int(limit16), int(limit8)), "flbm_set_pull_format",
+           ctx)
+
+
+def flbm_pull_format_info(ctx):
+    """(format, tiles with 8-bit codes, tiles with 16-bit codes, tiles)."""
+    f, t8, t16, t = _I32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().flbm_pull_format_info(ctx, ctypes.byref(f), ctypes.byref(t8), ctypes.byref(t16),
+                                                ctypes.byref(t)), "flbm_pull_format_info", ctx)
+    return int(f.value), int(t8.value), int(t16.value), int(t.value)
+
+
+def flbm_get_compact_pull(ctx, n_pad: int, tiles: int):
+    """Host copy of the compact pull table: 16-bit codes uint32 [9][n_pad],
+    8-bit codes uint32 [4][n_pad] and uint16 [n_pad], header int32
+    [tiles][PULL_HDR]."""
+    codes16 = np.empty((9, n_pad), np.uint32)
+    codes8 = np.empty((4, n_pad), np.uint32)
+    tail = np.empty(n_pad, np.uint16)
+    hdr = np.empty((tiles, PULL_HDR), np.int32)
+    _check(load_library().flbm_get_compact_pull(ctx, codes16.ctypes.data, codes8.ctypes.data, tail.ctypes.data,
+                                                hdr.ctypes.data), "flbm_get_compact_pull", ctx)
+    return codes16, codes8, tail, hdr
 
 
 def flbm_state_bytes(ctx) -> int:
@@ -684,6 +715,18 @@ class Lattice:
 
     def pull_table(self):
         return flbm_get_pull_table(self.ctx, self.n_sites)
+
+    def set_pull_format(self, fmt: int, limit16: int = 0, limit8: int = 0):
+        flbm_set_pull_format(self.ctx, fmt, limit16, limit8)
+
+    def pull_format(self):
+        """(format, tiles with 8-bit codes, tiles with 16-bit codes, tiles)."""
+        return flbm_pull_format_info(self.ctx)
+
+    def compact_pull(self):
+        _, _, _, tiles = flbm_pull_format_info(self.ctx)
+        _, _, n_pad = flbm_device_layout(self.ctx)
+        return flbm_get_compact_pull(self.ctx, n_pad, tiles)
 
     def save_state(self) -> bytes:
         return flbm_save_state(self.ctx)

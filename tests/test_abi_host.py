@@ -183,3 +183,113 @@ def test_batch_and_network_argument_checks_without_a_device():
     assert lib.flbm_batch_set_schedule(None, None) == fluxlbm.FLBM_EINVAL
     assert lib.flbm_gemm_bf16(None, 1, 1, None, 1, 1, None, 1, 1, 1, 1, None) == fluxlbm.FLBM_EINVAL
     assert lib.flbm_set_controller(None, None, None) == fluxlbm.FLBM_EINVAL
+
+
+_OPP = [0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17]
+
+
+def _decode_compact(codes16, codes8, tail, hdr, npad, n):
+    """Flat pull indices [18][n] that the coded tiles give, and each site's
+    tile form (0: int32 table, 1: 16-bit codes, 2: 8-bit codes)."""
+    tile = npad // hdr.shape[0]
+    s = np.arange(n)
+    t = s // tile
+    p = s % tile
+    form = hdr[t, 18]
+    out = np.full((18, n), -1, np.int64)
+    for q in range(1, 19):
+        base = hdr[t, q - 1].astype(np.int64)
+        c16 = (codes16[(q - 1) // 2, :n].astype(np.int64) >> (16 * ((q - 1) % 2))) & 0xFFFF
+        d16 = np.where(c16 == 0xFFFE, 19 * npad, np.where(c16 == 0xFFFF, _OPP[q] * npad + s, base + c16))
+        if q <= 16:
+            c8 = (codes8[(q - 1) // 4, :n].astype(np.int64) >> (8 * ((q - 1) % 4))) & 0xFF
+        else:
+            c8 = (tail[:n].astype(np.int64) >> (8 * (q - 17))) & 0xFF
+        d8 = np.where(c8 == 0xFE, 19 * npad, np.where(c8 == 0xFF, _OPP[q] * npad + s, base + p + c8))
+        out[q - 1] = np.where(form == 1, d16, np.where(form == 2, d8, -1))
+    return out, form
+
+
+def _compact(ctx):
+    n, _, _ = fluxlbm.flbm_num_sites(ctx)
+    _, _, npad = fluxlbm.flbm_device_layout(ctx)
+    fmt, t8, t16, tiles = fluxlbm.flbm_pull_format_info(ctx)
+    codes16, codes8, tail, hdr = fluxlbm.flbm_get_compact_pull(ctx, npad, tiles)
+    got, form = _decode_compact(codes16, codes8, tail, hdr, npad, n)
+    return n, npad, (fmt, t8, t16, tiles), got, form, (codes16, codes8, tail, hdr)
+
+
+@pytest.mark.parametrize("z_mode", [0, 1, 2])
+@pytest.mark.parametrize("px,py", [(0, 0), (1, 1)])
+@pytest.mark.parametrize("fmt", [1, 2])
+def test_compact_pull_table_decodes_to_the_definition(z_mode, px, py, fmt):
+    mask = inputs.random_mask((9, 23, 17), 0.3, 40 + z_mode)
+    mask[0, 0, 0] = 0
+    ctx = fluxlbm.flbm_create(mask, _params(mask, periodic_x=px, periodic_y=py, z_mode=z_mode))
+    try:
+        assert fluxlbm.flbm_pull_format_info(ctx)[0] == fluxlbm.FLBM_PULL_COMPACT  # the default
+        fluxlbm.flbm_set_pull_format(ctx, fmt)
+        n, npad, info, got, form, (_, _, _, hdr) = _compact(ctx)
+        assert info[0] == fmt and info[3] == npad // 512
+        assert info[1] + info[2] == info[3]          # no tile of this small box needs int32
+        if fmt == fluxlbm.FLBM_PULL_HALF:
+            assert info[1] == 0
+        assert np.array_equal(got, _brute_pull(mask, px, py, z_mode, npad))
+        assert not hdr[:, 19].any()
+    finally:
+        fluxlbm.flbm_destroy(ctx)
+
+
+def test_compact_pull_table_falls_back_per_tile():
+    # a 48^3 pack with reservoirs; small code limits send the tiles whose
+    # sources spread wider (a y-wrap, sources a plane apart) to wider forms
+    mask, _, _ = inputs.sphere_pack(48, 0.35, seed=7, reservoir_layers=4)
+    ctx = fluxlbm.flbm_create(mask, _params(mask))
+    try:
+        n, npad, info, _, _, _ = _compact(ctx)
+        nbr = fluxlbm.flbm_get_pull_table(ctx, n).astype(np.int64)
+        tiles = info[3]
+        assert 0 < info[1] < tiles and info[1] + info[2] == tiles  # byte and 16-bit tiles, no int32
+        fluxlbm.flbm_set_pull_format(ctx, fluxlbm.FLBM_PULL_COMPACT, 600, 100)
+        n, npad, info, got, form, (c16, c8, tail, hdr) = _compact(ctx)
+        assert info[1] > 0 and info[2] > 0 and info[1] + info[2] < tiles   # all three forms
+        coded = form > 0
+        assert np.array_equal(got[:, coded], nbr[:, coded])
+        # rows of the forms a tile does not use are zero, and int32 tiles have no header
+        t_form = hdr[:, 18]
+        assert not hdr[t_form == 0].any()
+        assert not c16.reshape(9, tiles, 512)[:, t_form != 1].any()
+        assert not c8.reshape(4, tiles, 512)[:, t_form != 2].any()
+        assert not tail.reshape(tiles, 512)[t_form != 2].any()
+        # an int32 tile really spans more than the 16-bit limit in some direction
+        t = int(np.flatnonzero(t_form == 0)[0])
+        rows = nbr[:, t * 512:min(n, (t + 1) * 512)]
+        spans = [int(r[(r // npad) == q].max() - r[(r // npad) == q].min()) if ((r // npad) == q).any() else 0
+                 for q, r in zip(range(1, 19), rows)]
+        assert max(spans) > 600
+        # defaults again; 16-bit only; then the int32 table
+        fluxlbm.flbm_set_pull_format(ctx, fluxlbm.FLBM_PULL_COMPACT)
+        assert fluxlbm.flbm_pull_format_info(ctx)[1:3] == tuple(_compact(ctx)[2][1:3])
+        fluxlbm.flbm_set_pull_format(ctx, fluxlbm.FLBM_PULL_HALF)
+        assert fluxlbm.flbm_pull_format_info(ctx)[1:3] == (0, tiles)
+        fluxlbm.flbm_set_pull_format(ctx, fluxlbm.FLBM_PULL_INT32)
+        assert fluxlbm.flbm_pull_format_info(ctx) == (fluxlbm.FLBM_PULL_INT32, 0, 0, tiles)
+        for bad in ((7, 0, 0), (2, 0x10000, 0), (2, 0, 0x100), (2, -1, 0)):
+            with pytest.raises(fluxlbm.FlbmError):
+                fluxlbm.flbm_set_pull_format(ctx, *bad)
+    finally:
+        fluxlbm.flbm_destroy(ctx)
+
+
+def test_colour_model_has_no_compact_pull_table():
+    mask = inputs.random_mask((6, 8, 8), 0.2, 5)
+    mask[0] = 0
+    ctx = fluxlbm.flbm_create(mask, _params(mask, model=fluxlbm.FLBM_COLOUR))
+    try:
+        assert fluxlbm.flbm_pull_format_info(ctx)[:3] == (fluxlbm.FLBM_PULL_INT32, 0, 0)
+        for fmt in (fluxlbm.FLBM_PULL_HALF, fluxlbm.FLBM_PULL_COMPACT):
+            with pytest.raises(fluxlbm.FlbmError) as e:
+                fluxlbm.flbm_set_pull_format(ctx, fmt)
+            assert e.value.status == fluxlbm.FLBM_ESTATE
+    finally:
+        fluxlbm.flbm_destroy(ctx)
