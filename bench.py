@@ -95,10 +95,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str, n_sites: int):
+def measured_traffic(workload: str, precision: str, n_sites: int, pull: str = "compact"):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary of this workload, or None when there is none or the
-    kernel sources changed since the counters were taken."""
+    counter summary of this workload, or None when there is none, it was
+    taken with another pull-table format, or the kernel sources changed
+    since the counters were taken."""
     path = os.path.join(PROFILE_DIR, f"k_stream_collide_{workload}_{precision}.md")
     if not os.path.exists(path):
         return None
@@ -108,7 +109,7 @@ def measured_traffic(workload: str, precision: str, n_sites: int):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("pull_table", "int32") != pull:
         return None
     try:
         per_site = float(vals["hbm_bytes_per_site"])
@@ -395,7 +396,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(args.config, kw["precision"], n),
+        "traffic": measured_traffic(args.config, kw["precision"], n, args.pull),
         "kernel": "k_phase+k_colour" if kw.get("model") == "colour" else "k_stream_collide",
         "kernel_ms": round(ms_kernel, 5),
         "plane_kernel_ms": round(ms_plane, 5),

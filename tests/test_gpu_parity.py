@@ -252,6 +252,8 @@ def test_steady_flux_and_permeability_match_fp64(precision, tol):
         runs[prec] = (0.5 * (h[-1, 2] + h[-2, 2]), h[:, 0].mean() - 1.0)
         lat.close()
     (q64, d64), (qp, dp) = runs["fp64"], runs[precision]
+    print(f"steady {precision}: Q_out/Q* FP64 {q64 / q:.6f}, {precision} vs FP64 {qp / q64 - 1:+.3e}, "
+          f"density difference vs FP64 {dp / d64 - 1:+.3e}", flush=True)
     assert abs(q64 - q) <= 0.1 * q                  # FP64 is well into the approach
     assert abs(qp - q64) <= tol * q, (qp / q - 1, q64 / q - 1)
     assert abs(dp - d64) <= tol * d64, (dp / d64 - 1)
