@@ -304,7 +304,8 @@ typedef struct flbm_schedule {
     int32_t tiles_per_item; /* consecutive tiles of one sample per work item (>= 1) */
     int32_t chunk;          /* steps per captured graph (>= 1; graphs are used when even) */
     int32_t occupancy;      /* 0: the compiler's register budget; 8: at most 64 VGPRs (8 waves per
-                               SIMD); only for grid 0 with one tile per item */
+                               SIMD) for the steps that record no observables; only for grid 0
+                               with one tile per item */
 } flbm_schedule;
 
 /* samples: n context pointers (not copied beyond the call's lifetime of the

@@ -1581,9 +1581,12 @@ void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
 {
     const int grid = b->sched.grid > 0 ? std::min(b->sched.grid, b->n_work) : b->n_work;
     if (b->sched.grid == 0 && b->sched.tiles_per_item == 1) {
-        // one tile per block: the loop-free kernel, in the chosen register budget
+        // one tile per block: the loop-free kernel, in the chosen register budget.
+        // The observable step always takes the compiler's budget: squeezed to
+        // 64 VGPRs it spills to scratch, and a scratch-using launch inside a
+        // captured chunk costs far more than the step itself.
         const dim3 g(b->n_work), blk(SC_BLOCK);
-        const bool o8 = b->sched.occupancy == 8;
+        const bool o8 = b->sched.occupancy == 8 && !obs;
 #define FLBM_BATCH_TILE(OB, BU)                                                                           \
     do {                                                                                                  \
         if (o8)                                                                                           \
