@@ -1,0 +1,73 @@
+"""Parity at the full size of the benchmark workload: the 256^3 sphere pack
+(porosity 0.35, 6 + 6 reservoir layers, 6.29M pore sites, Darcy velocity
+1e-4, tau 0.8), stepped exactly as the benchmark steps it (the compact pull
+table, the same launch), against the FP64 oracle on every site. One step
+from a seeded random state near equilibrium; the per-step tolerances are
+those of the small cases (FP32 1e-6, FP16 deviations 5e-5, relative to the
+largest value). A few more steps then check what holds at any size: the
+inlet flux equals its target every step."""
+import numpy as np
+import pytest
+
+import bench
+from paper_1806_10589_amd import fluxlbm
+
+from .gpu_helpers import dense_to_sites, load_same_state, pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("fp16dev", 5e-5)])
+def test_bench_workload_one_step_against_oracle(precision, tol):
+    mask, kw, _ = bench.make_workload(bench.CONFIGS["pack256"])
+    print(f"full size: {precision}, mask {mask.shape}", flush=True)
+    lat, orc = pair(mask, precision=precision, tau=kw["tau"], q_target=kw["q_target"],
+                    periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
+    try:
+        fmt, t8, t16, tiles = lat.pull_format()
+        assert fmt == fluxlbm.FLBM_PULL_COMPACT and t8 > 0.8 * tiles
+        load_same_state(lat, orc, mask, 77, amp=0.02)
+        lat.step(1)
+        h_orc = orc.step(1)
+        err = rel_err(lat.read_distributions(), dense_to_sites(mask, orc.get_f()))
+        h = lat.history(1)
+        print(f"full size {precision}: one-step error {err:.3e}, rho_in {h[0, 0]:.12f} vs {h_orc[0, 0]:.12f}",
+              flush=True)
+        assert err <= tol
+        assert abs(h[0, 0] - h_orc[0, 0]) <= (1e-7 if precision == "fp32" else 1e-5)
+        assert abs(h[0, 1] - kw["q_target"]) <= 1e-9 * kw["q_target"]
+        lat.step(20)
+        assert lat.sync() == fluxlbm.FLBM_OK
+        hq = lat.history(20)[:, 1]
+        assert np.abs(hq - kw["q_target"]).max() <= (1e-9 if precision == "fp32" else 1e-6) * kw["q_target"]
+    finally:
+        lat.close()
+        del orc
+
+
+def test_largest_workload_properties():
+    """The 512^3 pack (porosity 0.25, 35.5M pore sites, the largest single
+    lattice of the benchmarks): too large for the dense oracle, so the
+    properties that hold at any size -- the inlet flux equals its target at
+    every step, the state stays finite and subsonic, and the compact table
+    addresses the same slots as the int32 one (one step each way, bitwise)."""
+    mask, kw, _ = bench.make_workload(bench.CONFIGS["pack512"])
+    print(f"largest: mask {mask.shape}", flush=True)
+    outs = []
+    for fmt in (fluxlbm.FLBM_PULL_COMPACT, fluxlbm.FLBM_PULL_INT32):
+        lat = fluxlbm.Lattice(mask, watchdog_every=8, **kw)
+        try:
+            lat.set_pull_format(fmt)
+            lat.init_equilibrium(1.0)
+            lat.step(16)
+            assert lat.sync() == fluxlbm.FLBM_OK
+            h = lat.history(16)
+            assert np.abs(h[:, 1] - kw["q_target"]).max() <= 1e-9 * kw["q_target"]
+            m, umax, bad = lat.observables()
+            assert bad == 0 and umax < 0.1
+            f = lat.read_distributions()
+            outs.append((f[:, ::997].copy(), h[:, :3].copy()))
+            del f
+        finally:
+            lat.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
