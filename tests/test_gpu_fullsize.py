@@ -71,3 +71,77 @@ def test_largest_workload_properties():
         finally:
             lat.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_colour_full_pack_properties():
+    """The two-fluid configuration at full size: the 384^3 pack (porosity
+    0.30, 18M pore sites) between a non-wetting reservoir (inlet side) and a
+    wetting reservoir of six pure-fluid layers each (the drainage protocol),
+    non-wetting fluid injected at capillary number 1e-5 (the 64^3 crop is
+    checked against the oracle element by element). At this size: the inlet
+    flux equals its target every step, the state stays finite and subsonic,
+    the phase field stays in [-1, 1], and -- while the interface is far from
+    both faces -- the wetting colour leaves only through the outlet, at the
+    fluid's outflow (B changes by -sum Q_out, to the density's deviation
+    from one in the outlet's pressure wave)."""
+    from paper_1806_10589_amd import inputs
+    mask, phi, _ = inputs.sphere_pack(384, 0.30, seed=3, reservoir_layers=6)
+    print(f"colour full: mask {mask.shape}, porosity {phi:.3f}", flush=True)
+    q = 1e-5 * 0.01 * 0.30 * 384 * 384 / (1.0 / 6.0)   # Q* = Ca gamma eps A / mu_w, mu_w = 1/6
+    lat = fluxlbm.Lattice(mask, precision="fp32", model="colour", tau=1.0, alpha=0.01, beta=0.7,
+                          phi_solid=-0.7071, q_target=q, watchdog_every=10)
+    try:
+        z = lat.coords()[:, 2]
+        na = (z < 6).astype(float)
+        lat.init_colour(na, 1.0 - na)
+        b0 = lat.read_colour()[1].sum()
+        n = 40
+        lat.step(n)
+        assert lat.sync() == fluxlbm.FLBM_OK
+        h = lat.history(n)
+        assert np.abs(h[:, 1] - q).max() <= 1e-9 * q
+        m, umax, bad = lat.observables()
+        assert bad == 0 and umax < 0.1
+        ph = lat.phase()
+        assert np.isfinite(ph).all() and ph.min() >= -1.0 - 1e-6 and ph.max() <= 1.0 + 1e-6
+        db = lat.read_colour()[1].sum() - b0
+        out = h[:, 2].sum()
+        print(f"colour full: wetting change {db:.4f}, -sum Q_out {-out:.4f}", flush=True)
+        # the colour leaves at N_B u_z per outlet site: in the first steps'
+        # pressure wave N_B deviates from one by a few per cent (measured 3 %)
+        assert abs(db + out) <= 5e-2 * abs(out)
+    finally:
+        lat.close()
+
+
+def test_batch64_full_size():
+    """The batched configuration at full size: 64 packs of uneven size (66M
+    pore sites) stepped by one launch per step under the schedule the
+    autotuner picks; each sample's inlet flux equals its own target every
+    step, and two samples (the smallest and the largest) equal their own
+    single-lattice runs bit for bit."""
+    samples = bench.batch_samples(bench.CONFIGS["batch64"])
+    print(f"batch64: {len(samples)} samples", flush=True)
+    lats = [fluxlbm.Lattice(m, watchdog_every=1000, **kw) for m, kw, _ in samples]
+    sizes = [l.n_sites for l in lats]
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes))]
+    singles = [fluxlbm.Lattice(samples[i][0], watchdog_every=1000, **samples[i][1]) for i in pick]
+    b = fluxlbm.Batch(lats)
+    try:
+        b.autotune(None, 2)
+        for l in lats + singles:
+            l.init_equilibrium(1.0)
+        n = 24
+        b.step(n)
+        rc, bad = b.sync()
+        assert rc == fluxlbm.FLBM_OK and bad == -1
+        for l, (m, kw, _) in zip(lats, samples):
+            h = l.history(n)
+            assert np.abs(h[:, 1] - kw["q_target"]).max() <= 1e-9 * kw["q_target"]
+        for s, i in zip(singles, pick):
+            s.step(n)
+            assert np.array_equal(s.read_distributions(), lats[i].read_distributions())
+    finally:
+        b.close()
+        for l in lats + singles:
+            l.close()
