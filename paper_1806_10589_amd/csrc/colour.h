@@ -126,7 +126,7 @@ struct ColourStepArgs {
 
 // Colour step: TILE threads per tile, one site per thread.
 template <typename T, bool OBS>
-__global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *__restrict__ fout,
+__global__ __launch_bounds__(TILE, (sizeof(T) <= 4 && !OBS) ? 6 : 1) void k_colour(const T *__restrict__ fin, T *__restrict__ fout,
                                                  const int32_t *__restrict__ nbr, StepArgs a,
                                                  ColourStepArgs c)
 {
@@ -137,13 +137,22 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
     const int64_t npad = a.npad;
     const C *phi = (const C *)c.phi;
 
+    // pull f, and with the same indices the colour gradient: the neighbour
+    // x + xi_q is the source of pull direction opp(q), so
+    // C = -3 sum_p w_p xi_p phi(source of p)
     R g[19];
-    int32_t idx[19];
     g[0] = Codec<T>::dec(fin[s], 0);
+    const double own = (double)phi[s];
+    R gx = 0, gy = 0, gz = 0;
 #pragma unroll
     for (int q = 1; q < 19; ++q) {
-        idx[q] = nbr[(int64_t)(q - 1) * npad + s];
-        g[q] = Codec<T>::dec(fin[idx[q]], q);
+        const int32_t idx = nbr[(int64_t)(q - 1) * npad + s];
+        g[q] = Codec<T>::dec(fin[idx], q);
+        const R ph = (R)neighbour_phi(phi, idx, q, npad, c.sentinel, own, c.phi_solid);
+        const R w3 = (R)(3.0 * d3q19::weight(q));
+        if (d3q19::cx[q]) gx -= d3q19::cx[q] * w3 * ph;
+        if (d3q19::cy[q]) gy -= d3q19::cy[q] * w3 * ph;
+        if (d3q19::cz[q]) gz -= d3q19::cz[q] * w3 * ph;
     }
 
     double uz_in = 0.0, uz_out = 0.0;
@@ -152,19 +161,6 @@ __global__ __launch_bounds__(TILE) void k_colour(const T *__restrict__ fin, T *_
         uz_in = inlet_condition(g, drho_in, a.rho0);
     }
     if (tile >= a.tout0 && s >= a.out0 && s < a.n) uz_out = outlet_condition(g, a.st->drho_out, a.rho0);
-
-    // colour gradient: the neighbour x + xi_q is the source of pull
-    // direction opp(q), so C = -3 sum_p w_p xi_p phi(source of p)
-    const double own = (double)phi[s];
-    R gx = 0, gy = 0, gz = 0;
-#pragma unroll
-    for (int p = 1; p < 19; ++p) {
-        const R ph = (R)neighbour_phi(phi, idx[p], p, npad, c.sentinel, own, c.phi_solid);
-        const R w3 = (R)(3.0 * d3q19::weight(p));
-        if (d3q19::cx[p]) gx -= d3q19::cx[p] * w3 * ph;
-        if (d3q19::cy[p]) gy -= d3q19::cy[p] * w3 * ph;
-        if (d3q19::cz[p]) gz -= d3q19::cz[p] * w3 * ph;
-    }
 
     const R snu = (R)a.st->omega;
     const bool collide = snu != (R)0;
