@@ -117,13 +117,13 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
 flbm_status flbm_destroy(flbm_ctx *c);
 
 /* Device bytes the context needs (distributions in two copies, the int32
- * pull table, FP64 reduction scratch and history). */
+ * pull table and its compact form, FP64 reduction scratch and history). */
 flbm_status flbm_device_bytes(const flbm_ctx *c, size_t *bytes);
 
 /* Use caller-owned device memory (e.g. a torch uint8 tensor) of at least
  * flbm_device_bytes bytes, 256-byte aligned; it must outlive the context.
  * Only valid before any device memory is in use (else FLBM_ESTATE).
- * Uploads the pull table and sets the rest state rho = rho_out, u = 0.
+ * Uploads the pull tables and sets the rest state rho = rho_out, u = 0.
  * Errors: FLBM_EBOUND if too small, FLBM_EINVAL if null or misaligned. */
 flbm_status flbm_bind_device_memory(flbm_ctx *c, void *dev_ptr, size_t bytes);
 

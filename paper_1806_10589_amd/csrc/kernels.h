@@ -36,7 +36,7 @@ constexpr bool SC_NT = FLBM_SC_NT;  // non-temporal stores of the new state
 #ifndef FLBM_SC_IDX_NT
 #define FLBM_SC_IDX_NT 1
 #endif
-constexpr int SC_IDX_AUX = FLBM_SC_IDX_NT ? 2 : 0;  // cache policy of the pull-index loads
+constexpr int SC_IDX_AUX = FLBM_SC_IDX_NT ? 2 : 0;  // cache policy of the pull-table loads (codes or indices)
 constexpr int SC_V = FLBM_SC_V;
 constexpr int TILE = SC_BLOCK * SC_V;
 constexpr int PAD_SITES = 1024;  // n_pad is a multiple of this (>= every TILE used)
