@@ -343,7 +343,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the z-slab sharding design is described in DESIGN.md)", file=sys.stderr)
+              "(sharding the lattice into z-slabs with a halo exchange per step is a design only)", file=sys.stderr)
         sys.exit(2)
 
     import torch
