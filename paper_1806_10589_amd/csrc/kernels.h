@@ -156,15 +156,18 @@ struct PlaneArgs {
 // the outlet flux of a 256^3 pack at Darcy velocity 1e-5 ends 7 % low).
 // In the FP16 normal range the FP16 grid is the FP32 values whose 13 low
 // significand bits are zero, so the dither is an integer add of 13 random
-// bits to the FP32 pattern and a mask. The bits come from one integer hash
+// bits to the FP32 pattern and a mask. gfx950's stochastic-rounding
+// conversion (v_cvt_sr_f16_f32) does exactly that in one instruction: it adds
+// the top 13 bits of its 32-bit random operand to the 13 dropped bits and
+// truncates (checked bit for bit against the add-and-mask form on a million
+// FP16-normal values); below the FP16 normal range it rounds onto the
+// subnormal grid the same way. The random word comes from one integer hash
 // of the site (shared by its 19 populations), xored with a constant per
 // direction and multiplied by an odd constant: the top bits of the product
 // differ between the directions of a site in no fixed pattern. (Offsets that
 // differ between directions by a fixed amount at every site -- a Weyl step
 // -- bias the steady flux by 1 % on a test pack; independent ones leave
 // 0.1-0.2 %.) They depend on nothing else, so runs stay deterministic.
-// Below the FP16 normal range the conversion rounds the masked value once
-// more to nearest.
 __device__ __forceinline__ uint32_t dither_hash(uint32_t x)
 {
     x ^= x >> 16;
@@ -182,16 +185,18 @@ template <typename T> struct Codec {
 };
 template <> struct Codec<_Float16> {
     typedef float R;
-    static __device__ __forceinline__ float dec(_Float16 v, int q)
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    static __device__ __forceinline__ float scale(int q) { return (float)(1u << d3q19::half_shift(q)); }
+    static __device__ __forceinline__ float dec(_Float16 v, int q) { return (float)v * (1.0f / scale(q)); }
+    // x: the value already scaled, g_q 2^half_shift(q)
+    static __device__ __forceinline__ _Float16 enc_scaled(float x, int q, uint32_t site)
     {
-        return (float)v * (1.0f / (float)(1u << d3q19::half_shift(q)));
+        const uint32_t r = (dither_hash(site) ^ ((uint32_t)q * 0x9e3779b9u)) * 0x85ebca6bu;
+        return __builtin_amdgcn_cvt_sr_f16_f32(h2{0, 0}, x, r, false)[0];
     }
     static __device__ __forceinline__ _Float16 enc(float v, int q, uint32_t site)
     {
-        const float x = v * (float)(1u << d3q19::half_shift(q));
-        const uint32_t r = ((dither_hash(site) ^ ((uint32_t)q * 0x9e3779b9u)) * 0x85ebca6bu) >> 19;  // 13 bits
-        const uint32_t b = (__builtin_bit_cast(uint32_t, x) + r) & 0xffffe000u;
-        return (_Float16)__builtin_bit_cast(float, b);
+        return enc_scaled(v * scale(q), q, site);
     }
 };
 template <typename T> struct Compute { using type = typename Codec<T>::R; };
@@ -449,19 +454,29 @@ __device__ __forceinline__ double outlet_condition(R (&g)[19], double drho_out, 
 // the odd part omega w rho0 3 xi.u; omega and the weights are folded into
 // per-class coefficients.
 // On return g holds the post-collision deviations; drho, u the moments.
-template <typename R>
+// SCALED: g holds the FP16 storage scaling of the deviations, g_q
+// 2^half_shift(q), on entry and on return; the moment sums take the inverse
+// powers of two and the relaxation coefficients the powers of two. Scaling by
+// a power of two commutes with rounding, so the result is the unscaled
+// computation's, scaled, without a multiply per population on either side.
+template <typename R, bool SCALED = false>
 __device__ __forceinline__ void bgk_collide(R (&g)[19], R omega, R rho0, R inv_rho0, R &drho,
                                             R &ux, R &uy, R &uz)
 {
-    R d = g[0];
+    // per weight class (rest, axis, diagonal): the storage scale, 1 unless SCALED
+    constexpr double c0 = SCALED ? (double)(1u << d3q19::half_shift(0)) : 1.0;
+    constexpr double c1 = SCALED ? (double)(1u << d3q19::half_shift(1)) : 1.0;
+    constexpr double c2 = SCALED ? (double)(1u << d3q19::half_shift(7)) : 1.0;
+    R d = g[0] * (R)(1.0 / c0);
     R jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 1; q < 19; q += 2) {
+        const R inv = (R)(1.0 / (q <= 6 ? c1 : c2));
         const R sum = g[q] + g[q + 1], dif = g[q] - g[q + 1];
-        d += sum;
-        if (d3q19::cx[q]) jx += d3q19::cx[q] > 0 ? dif : -dif;
-        if (d3q19::cy[q]) jy += d3q19::cy[q] > 0 ? dif : -dif;
-        if (d3q19::cz[q]) jz += d3q19::cz[q] > 0 ? dif : -dif;
+        d += sum * inv;
+        if (d3q19::cx[q]) jx += (d3q19::cx[q] > 0 ? dif : -dif) * inv;
+        if (d3q19::cy[q]) jy += (d3q19::cy[q] > 0 ? dif : -dif) * inv;
+        if (d3q19::cz[q]) jz += (d3q19::cz[q] > 0 ? dif : -dif) * inv;
     }
     ux = jx * inv_rho0;
     uy = jy * inv_rho0;
@@ -470,10 +485,10 @@ __device__ __forceinline__ void bgk_collide(R (&g)[19], R omega, R rho0, R inv_r
     const R keep = (R)1 - omega;
     const R base = d - rho0 * (R)1.5 * (ux * ux + uy * uy + uz * uz);
     // omega * w * base for the three weight classes, omega * w * rho0 * {9/2, 3}
-    const R ob0 = omega * (R)(1.0 / 3.0) * base;
-    const R ob1 = omega * (R)(1.0 / 18.0) * base, ob2 = omega * (R)(1.0 / 36.0) * base;
-    const R oe1 = omega * rho0 * (R)(4.5 / 18.0), oe2 = omega * rho0 * (R)(4.5 / 36.0);
-    const R oo1 = omega * rho0 * (R)(3.0 / 18.0), oo2 = omega * rho0 * (R)(3.0 / 36.0);
+    const R ob0 = omega * (R)(c0 / 3.0) * base;
+    const R ob1 = omega * (R)(c1 / 18.0) * base, ob2 = omega * (R)(c2 / 36.0) * base;
+    const R oe1 = omega * rho0 * (R)(c1 * 4.5 / 18.0), oe2 = omega * rho0 * (R)(c2 * 4.5 / 36.0);
+    const R oo1 = omega * rho0 * (R)(c1 * 3.0 / 18.0), oo2 = omega * rho0 * (R)(c2 * 3.0 / 36.0);
     g[0] = keep * g[0] + ob0;
 #pragma unroll
     for (int q = 1; q < 19; q += 2) {  // q has positive orientation, q + 1 = opp(q)
@@ -652,11 +667,17 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
 // Encode a collided site for storage, mass-exact (see above): h[q] for
 // q >= 1 first, then the rest population from the pre-collision mass minus
 // what the others hold as stored.
-template <typename T, typename R>
+// SCALED: g holds the FP16 storage scaling (see bgk_collide).
+template <typename T, bool SCALED = false, typename R>
 __device__ __forceinline__ void encode_site(const R (&g)[19], T (&h)[19], R pre, uint32_t site)
 {
 #pragma unroll
-    for (int q = 1; q < 19; ++q) h[q] = Codec<T>::enc(g[q], q, site);
+    for (int q = 1; q < 19; ++q) {
+        if constexpr (SCALED)
+            h[q] = Codec<T>::enc_scaled(g[q], q, site);
+        else
+            h[q] = Codec<T>::enc(g[q], q, site);
+    }
     if constexpr (!std::is_same<T, double>::value) {
         R s = 0;
 #pragma unroll
@@ -678,6 +699,28 @@ __device__ __forceinline__ void conserve_mass(R (&g)[19], R pre, uint32_t site)
     }
 }
 
+// A loaded population as the step's arithmetic holds it: decoded, or for
+// SCALED only widened (it keeps the storage scaling).
+template <typename T, bool SCALED>
+__device__ __forceinline__ typename Compute<T>::type load_pop(T v, int q)
+{
+    if constexpr (SCALED)
+        return (typename Compute<T>::type)v;
+    else
+        return Codec<T>::dec(v, q);
+}
+
+// SCALED populations to deviations (UP false) and back (UP true), around the
+// boundary conditions of the few inlet and outlet sites; exact.
+template <typename T, bool SCALED, bool UP, typename R>
+__device__ __forceinline__ void rescale_pops(R (&g)[19])
+{
+    if constexpr (SCALED) {
+#pragma unroll
+        for (int q = 0; q < 19; ++q) g[q] *= UP ? Codec<T>::scale(q) : (R)1 / Codec<T>::scale(q);
+    }
+}
+
 // The work of one tile (SC_BLOCK threads), shared by the single-lattice
 // kernel (one tile per block) and the batched kernel (a work list of tiles
 // of many lattices per block).
@@ -688,6 +731,9 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
 {
     using R = typename Compute<T>::type;
     constexpr int V = SC_V;
+    // FP16 with BGK keeps the populations in their storage scaling from load
+    // to store (see bgk_collide)
+    constexpr bool SCALED = std::is_same<T, _Float16>::value && !MRT;
     const int64_t s0 = ((int64_t)tile * SC_BLOCK + threadIdx.x) * V;
     const int64_t npad = a.npad;
 
@@ -701,7 +747,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
             T r[V];
             buf_load_v<V, T, T>(rf, vo, 0u, r);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v][0] = Codec<T>::dec(r[v], 0);
+            for (int v = 0; v < V; ++v) g[v][0] = load_pop<T, SCALED>(r[v], 0);
         }
         const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
         const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
@@ -730,7 +776,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
                                          : (c == PULL_BYTE_BOUNCE ? bb + (uint32_t)v : sent);
                     T r[1];
                     buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
-                    g[v][q] = Codec<T>::dec(r[0], q);
+                    g[v][q] = load_pop<T, SCALED>(r[0], q);
                 }
             }
         } else if (form == PULL_TILE_HALF) {
@@ -752,7 +798,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
                                              : (c == PULL_BOUNCE ? bb + (uint32_t)v : sent);
                         T r[1];
                         buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
-                        g[v][q] = Codec<T>::dec(r[0], q);
+                        g[v][q] = load_pop<T, SCALED>(r[0], q);
                     }
                 }
             }
@@ -765,7 +811,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
                 for (int v = 0; v < V; ++v) {
                     T r[1];
                     buf_load_v<1, T, T>(rf, (uint32_t)idx[v] * (uint32_t)sizeof(T), 0u, r);
-                    g[v][q] = Codec<T>::dec(r[0], q);
+                    g[v][q] = load_pop<T, SCALED>(r[0], q);
                 }
             }
         }
@@ -774,14 +820,14 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
             T r[V];
             load_v<V>(fin + s0, r);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v][0] = Codec<T>::dec(r[v], 0);
+            for (int v = 0; v < V; ++v) g[v][0] = load_pop<T, SCALED>(r[v], 0);
         }
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
             int32_t idx[V];
             load_v<V>(nbr + (int64_t)(q - 1) * npad + s0, idx);
 #pragma unroll
-            for (int v = 0; v < V; ++v) g[v][q] = Codec<T>::dec(fin[idx[v]], q);
+            for (int v = 0; v < V; ++v) g[v][q] = load_pop<T, SCALED>(fin[idx[v]], q);
         }
     }
 
@@ -790,12 +836,20 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         const double drho_in = inlet_drho(a.st, rd, a.rho0, a.a_in);
 #pragma unroll
         for (int v = 0; v < V; ++v)
-            if (s0 + v < a.a_in) uz_in += inlet_condition(g[v], drho_in, a.rho0);
+            if (s0 + v < a.a_in) {
+                rescale_pops<T, SCALED, false>(g[v]);
+                uz_in += inlet_condition(g[v], drho_in, a.rho0);
+                rescale_pops<T, SCALED, true>(g[v]);
+            }
     }
     if (tile >= a.tout0) {
 #pragma unroll
         for (int v = 0; v < V; ++v)
-            if (s0 + v >= a.out0 && s0 + v < a.n) uz_out += outlet_condition(g[v], a.st->drho_out, a.rho0);
+            if (s0 + v >= a.out0 && s0 + v < a.n) {
+                rescale_pops<T, SCALED, false>(g[v]);
+                uz_out += outlet_condition(g[v], a.st->drho_out, a.rho0);
+                rescale_pops<T, SCALED, true>(g[v]);
+            }
     }
 
     const R omega = (R)a.st->omega;
@@ -813,9 +867,9 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
                 bgk_collide(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
             }
         } else {
-            bgk_collide(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
+            bgk_collide<R, SCALED>(g[v], omega, (R)a.rho0, (R)a.inv_rho0, drho, ux, uy, uz);
         }
-        encode_site<T>(g[v], h[v], drho, (uint32_t)(s0 + v));  // drho: the pre-collision mass
+        encode_site<T, SCALED>(g[v], h[v], drho, (uint32_t)(s0 + v));  // drho: the pre-collision mass
         if (OBS) {
             m += (double)drho;
             u2max = fmaxf(u2max, (float)(ux * ux + uy * uy + uz * uz));
