@@ -435,8 +435,8 @@ flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, doubl
 
 /* Stream-copy calibration kernel: copies `bytes` (a multiple of 16, both
  * pointers 16-byte aligned) from src to dst on `hip_stream`, 16 bytes per
- * lane with non-temporal stores. For measuring attainable HBM bandwidth
- * beside the step. */
+ * lane with non-temporal loads and stores. For measuring attainable HBM
+ * bandwidth beside the step. */
 flbm_status flbm_copy_kernel(const void *src, void *dst, size_t bytes, void *hip_stream);
 
 const char *flbm_status_string(flbm_status s);
