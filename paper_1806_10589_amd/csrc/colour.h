@@ -104,9 +104,11 @@ __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
         nb += b[q];
     }
     const R tot = na + nb;
-    ((C *)p.na)[s] = (C)na;
-    ((C *)p.nb)[s] = (C)nb;
-    ((C *)p.phi)[s] = (C)(tot != (R)0 ? (na - nb) / tot : (R)0);
+    // non-temporal: the colour step reads these once per site (phi also from
+    // the neighbours), after the whole pass has been written
+    __builtin_nontemporal_store((C)na, &((C *)p.na)[s]);
+    __builtin_nontemporal_store((C)nb, &((C *)p.nb)[s]);
+    __builtin_nontemporal_store((C)(tot != (R)0 ? (na - nb) / tot : (R)0), &((C *)p.phi)[s]);
     if (p.st->omega == 0.0) {
         // testing aid (collision off): keep the streamed colours
 #pragma unroll
