@@ -235,7 +235,7 @@ __global__ __launch_bounds__(TILE, (sizeof(T) <= 4 && !OBS) ? 6 : 1) void k_colo
         u2max = (float)(ux * ux + uy * uy + uz * uz);
         bad = !isfinite((double)drho + (double)ux + (double)uy + (double)uz + (double)na + (double)nb);
     }
-    step_epilogue<TILE, OBS, true>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, a.rd, (double)na, (double)nb);
+    step_epilogue<TILE, OBS, true>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, (double)na, (double)nb);
 }
 
 // Phase field of a stored colour state (for readout): phi from the stored A, B.

@@ -53,7 +53,7 @@ struct flbm_ctx {
     std::string err;
 
     // launch geometry
-    int tiles = 0, nt_in = 0, nt01 = 0, tout0 = 0, n_bnd = 0, plane_blocks = 0;
+    int tiles = 0, nt_in = 0, nt01 = 0, tout0 = 0, plane_blocks = 0;
     int blocks256 = 0;  // n_pad / BLOCK: grid of the one-site-per-thread kernels
     bool use_buf = false; // f and nbr each below 4 GiB: buffer-instruction path
     bool need_plane = true; // the carried inlet sum is stale (state set from the host)
@@ -255,7 +255,6 @@ StepArgs step_args(const flbm_ctx *c)
     a.kcoef = c->kcoef;
     a.spart = c->spart;
     a.tout0 = flux ? c->tout0 : c->tiles;
-    a.n_bnd = c->n_bnd;
     a.hist_cap = HIST_CAP;
     const bool compact = c->pull_format != FLBM_PULL_INT32 && c->use_buf && c->pull.tiles > 0;
     a.pull_codes = compact ? c->pull_codes : nullptr;
@@ -384,6 +383,15 @@ void launch_stream_collide(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bo
         launch_stream_collide_c<T, false>(c, s, fin, fout, obs, a);
 }
 
+// The end of a step read from buffer `from` (after its step kernel): Q_in,
+// Q_out, the next inlet sum, the history record and the step counter.
+void launch_finalize(flbm_ctx *c, hipStream_t s, int from)
+{
+    StepArgs a = step_args(c);
+    a.rd = from;
+    hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(64), 0, s, a);
+}
+
 // Enqueue one step from buffer `from` on stream s.
 template <typename T>
 void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
@@ -391,6 +399,7 @@ void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
     const T *fin = (const T *)c->f[from];
     T *fout = (T *)c->f[from ^ 1];
     launch_stream_collide<T>(c, s, fin, fout, obs);
+    launch_finalize(c, s, from);
     if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
 }
 
@@ -398,6 +407,7 @@ void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
 {
     if (c->colour) {
         with_storage(c, [&](auto tag) { launch_colour_step<decltype(tag)>(c, s, from, obs); });
+        launch_finalize(c, s, from);
         if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
         return;
     }
@@ -769,13 +779,6 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
     c->nt_in = flux ? (int)((c->lat.a_in + TILE - 1) / TILE) : 0;
     c->nt01 = flux ? (int)((c->lat.n01 + TILE - 1) / TILE) : 0;
     c->tout0 = flux ? (int)((c->lat.n - c->lat.a_out) / TILE) : c->tiles;
-    if (flux) {
-        // boundary tiles: [0, nt01) (planes 0-1, including the inlet) and [tout0, tiles)
-        const int overlap = std::max(0, c->nt01 - c->tout0);
-        c->n_bnd = c->nt01 + (c->tiles - c->tout0) - overlap;
-    } else {
-        c->n_bnd = 1;
-    }
     c->plane_blocks = flux ? (int)std::min<int64_t>((c->lat.a_in + BLOCK - 1) / BLOCK, PLANE_MAX_BLOCKS) : 0;
     const int w = p->watchdog_every > 0 ? std::min(p->watchdog_every, 256) : 256;
     c->chunk = std::max(2, w + (w & 1));
@@ -1425,6 +1428,7 @@ flbm_status flbm_profile_kernels(flbm_ctx *c, int32_t n, double *ms_plane, doubl
             });
         }
         HIPCHK(c, hipEventRecord(ev[1], c->stream));
+        launch_finalize(c, c->stream, from);  // outside the timed step kernel
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipEventSynchronize(ev[1]));
         HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
@@ -1621,6 +1625,7 @@ void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
             hipLaunchKernelGGL((k_batch_step<T, false, false, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
                                b->d_work, b->n_work, parity);
     }
+    hipLaunchKernelGGL(k_batch_finalize, dim3((unsigned)b->s.size()), dim3(64), 0, s, b->d_tab, parity);
     if (obs)
         for (flbm_ctx *c : b->s)
             hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));

@@ -58,8 +58,7 @@ struct DevState {
     double obs_mass;      // on-demand observables
     double obs_umax;
     int64_t step;         // steps completed
-    uint32_t k_ticket;    // last-block tickets of the two reductions
-    uint32_t b_ticket;
+    uint32_t k_ticket;    // last-block ticket of the inlet-plane reduction
     uint32_t unstable;    // sticky watchdog flag
     uint32_t obs_bad;
     int64_t ctrl_steps;   // controller decisions taken
@@ -113,7 +112,6 @@ struct StepArgs {
     int32_t nt_in;        // tiles holding inlet sites: [0, nt_in)
     int32_t nt01;         // tiles holding planes 0 and 1: [0, nt01)
     int32_t tout0;        // tiles holding outlet sites: [tout0, tiles)
-    int32_t n_bnd;        // tiles taking part in the boundary ticket
     int32_t hist_cap;
     int32_t flux_mode;
     int32_t rd;           // s_carry slot this step reads (its input buffer)
@@ -533,13 +531,13 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
     k = block_sum<BLOCK>(k, lds);
     if (threadIdx.x == 0) {
         a.kpart[blockIdx.x] = k;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // the partial before the ticket
         const uint32_t prev = atomicAdd(&a.st->k_ticket, 1u);
         is_last = (prev == gridDim.x - 1);
     }
     __syncthreads();
     if (!is_last) return;
-    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every block's partial after its ticket
     double s = 0.0;
     for (int i = threadIdx.x; i < (int)gridDim.x; i += BLOCK) s += a.kpart[i];
     s = block_sum<BLOCK>(s, lds);
@@ -551,14 +549,12 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
 
 // Shared tail of the step kernels (NT threads per tile). OBS: write the
 // tile's watchdog partials (sum of rho - 1, max |u|^2, non-finite flag).
-// Boundary tiles (planes 0-1 and the outlet plane; tile 0 in a closed box)
-// reduce their u_z sums and their share of the next inlet sum; the last of
-// them to finish records the step (rho_in, Q_in, Q_out), hands the next
-// inlet sum over and advances the step counter.
+// Boundary tiles (planes 0-1 and the outlet plane) reduce their u_z sums and
+// their share of the next inlet sum, for k_step_finalize.
 // COLOUR: also the tile's sums of the two colour densities.
 template <int NT, bool OBS, bool COLOUR = false>
 __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_out, double s_next, double m,
-                                              float u2max, uint32_t bad, const StepArgs &a, const int rd,
+                                              float u2max, uint32_t bad, const StepArgs &a,
                                               double na_sum = 0.0, double nb_sum = 0.0)
 {
     __shared__ double lds[NT / 64];
@@ -596,35 +592,38 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
         }
     }
 
-    // Boundary tiles (planes 0-1 and the outlet plane; tile 0 in a closed
-    // box) reduce their partials; the last of them to finish records the
-    // step and hands the next inlet sum over.
-    const bool bnd_tile = a.flux_mode ? (tile < a.nt01 || tile >= a.tout0) : (tile == 0);
-    if (!bnd_tile) return;
-    __shared__ int is_last;
+    // Boundary tiles (planes 0-1 and the outlet plane) write their partial
+    // sums; k_step_finalize reduces them once the step kernel has ended.
+    if (!a.flux_mode || !(tile < a.nt01 || tile >= a.tout0)) return;
     const double si = block_sum<NT>(uz_in, lds);
     const double so = block_sum<NT>(uz_out, lds);
     const double sn = block_sum<NT>(s_next, lds);
     if (threadIdx.x == 0) {
         if (tile < a.nt_in) a.bpart_in[tile] = si;
-        if (a.flux_mode && tile < a.nt01) a.spart[tile] = sn;
-        if (a.flux_mode && tile >= a.tout0) a.bpart_out[tile - a.tout0] = so;
-        __threadfence();
-        const uint32_t prev = atomicAdd(&a.st->b_ticket, 1u);
-        is_last = (prev == (uint32_t)a.n_bnd - 1);
+        if (tile < a.nt01) a.spart[tile] = sn;
+        if (tile >= a.tout0) a.bpart_out[tile - a.tout0] = so;
     }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
+}
+
+// End of a step, launched after the step kernel (one wave): the sums of the
+// boundary tiles' partials give Q_in, Q_out and the inlet consistency sum the
+// next step starts from; the step goes into the history and the step counter
+// advances. A launch of its own rather than the last boundary tile to finish
+// (a ticket): the kernel boundary orders every tile's partial before these
+// reads, where the ticket needed a release fence per boundary tile, which
+// writes that XCD's L2 back, and cost about 7 % of the step on a 256^3 pack.
+__device__ __forceinline__ void finalize_step(const StepArgs &a, const int rd)
+{
+    const int nt_in = a.flux_mode ? a.nt_in : 0;
     const int nt_out = a.flux_mode ? (int)((a.npad / TILE) - a.tout0) : 0;
     const int nt01 = a.flux_mode ? a.nt01 : 0;
     double ti = 0.0, to = 0.0, tn = 0.0;
-    for (int i = threadIdx.x; i < a.nt_in; i += NT) ti += a.bpart_in[i];
-    for (int i = threadIdx.x; i < nt_out; i += NT) to += a.bpart_out[i];
-    for (int i = threadIdx.x; i < nt01; i += NT) tn += a.spart[i];
-    ti = block_sum<NT>(ti, lds);
-    to = block_sum<NT>(to, lds);
-    tn = block_sum<NT>(tn, lds);
+    for (int i = threadIdx.x; i < nt_in; i += 64) ti += a.bpart_in[i];
+    for (int i = threadIdx.x; i < nt_out; i += 64) to += a.bpart_out[i];
+    for (int i = threadIdx.x; i < nt01; i += 64) tn += a.spart[i];
+    ti = wave_sum(ti);
+    to = wave_sum(to);
+    tn = wave_sum(tn);
     if (threadIdx.x == 0) {
         DevState *st = a.st;
         const int64_t t = st->step;
@@ -643,8 +642,12 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
         h[6] = __builtin_nan("");
         h[7] = __builtin_nan("");
         st->step = t + 1;
-        st->b_ticket = 0;
     }
+}
+
+__global__ __launch_bounds__(64) void k_step_finalize(StepArgs a)
+{
+    finalize_step(a, a.rd);
 }
 
 // Fused step for every site: pull the 19 populations, apply the inlet or
@@ -916,7 +919,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         }
     }
 
-    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, rd);
+    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a);
 }
 
 template <typename T, bool OBS, bool BUF, bool MRT = false>
@@ -991,6 +994,13 @@ __global__ __launch_bounds__(SC_BLOCK, 8) void k_batch_tile8(const BatchSample *
                                                              const BatchItem *__restrict__ work, int32_t parity)
 {
     batch_tile_body<T, OBS, BUF, MRT>(tab, work, parity);
+}
+
+// End of a batched step: one wave per sample, as k_step_finalize.
+__global__ __launch_bounds__(64) void k_batch_finalize(const BatchSample *__restrict__ tab, int32_t parity)
+{
+    const StepArgs a = tab[blockIdx.x].a;
+    finalize_step(a, a.rd ^ parity);
 }
 
 // Reduce the per-tile observables of the last step into its history record
