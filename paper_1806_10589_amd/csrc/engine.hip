@@ -7,7 +7,7 @@
 // k_stream_collide pulls, applies the boundary conditions with the inlet
 // density of eq. potential, collides (BGK or MRT), stores, and writes per-tile
 // partials of Q_in, Q_out and of the inlet sum that the next step's inlet
-// sites will pull; k_step_finalize (one wave) reduces them. With pull streaming
+// sites will pull; k_step_finalize (one block) reduces them. With pull streaming
 // the "streamed" values of a step are gathers of the stored state, so no
 // grid-wide barrier is needed inside a step; k_inlet_plane computes the sum
 // from the state only after the host has written it. The colour model adds
@@ -390,7 +390,7 @@ void launch_finalize(flbm_ctx *c, hipStream_t s, int from)
 {
     StepArgs a = step_args(c);
     a.rd = from;
-    hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(FIN_BLOCK), 0, s, a);
 }
 
 // Enqueue one step from buffer `from` on stream s.
@@ -1479,7 +1479,7 @@ const char *flbm_last_error(const flbm_ctx *c) { return c ? c->err.c_str() : "";
 // ======================================================================
 // Batched stepping of many lattices (samples of uneven size, each with its
 // own target flux, outlet density and state) by one launch per step (and a
-// finalize launch with one wave per sample).
+// finalize launch with one block per sample).
 
 struct flbm_batch {
     std::vector<flbm_ctx *> s;
@@ -1627,7 +1627,7 @@ void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
             hipLaunchKernelGGL((k_batch_step<T, false, false, MRT>), dim3(grid), dim3(SC_BLOCK), 0, s, b->d_tab,
                                b->d_work, b->n_work, parity);
     }
-    hipLaunchKernelGGL(k_batch_finalize, dim3((unsigned)b->s.size()), dim3(64), 0, s, b->d_tab, parity);
+    hipLaunchKernelGGL(k_batch_finalize, dim3((unsigned)b->s.size()), dim3(FIN_BLOCK), 0, s, b->d_tab, parity);
     if (obs)
         for (flbm_ctx *c : b->s)
             hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));

@@ -605,25 +605,28 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
     }
 }
 
-// End of a step, launched after the step kernel (one wave): the sums of the
+// End of a step, launched after the step kernel (one block): the sums of the
 // boundary tiles' partials give Q_in, Q_out and the inlet consistency sum the
 // next step starts from; the step goes into the history and the step counter
 // advances. A launch of its own rather than the last boundary tile to finish
 // (a ticket): the kernel boundary orders every tile's partial before these
 // reads, where the ticket needed a release fence per boundary tile, which
 // writes that XCD's L2 back, and cost about 7 % of the step on a 256^3 pack.
+constexpr int FIN_BLOCK = 256;  // threads of a finalize: the partials in one round of loads
+
 __device__ __forceinline__ void finalize_step(const StepArgs &a, const int rd)
 {
+    __shared__ double lds[FIN_BLOCK / 64];
     const int nt_in = a.flux_mode ? a.nt_in : 0;
     const int nt_out = a.flux_mode ? (int)((a.npad / TILE) - a.tout0) : 0;
     const int nt01 = a.flux_mode ? a.nt01 : 0;
     double ti = 0.0, to = 0.0, tn = 0.0;
-    for (int i = threadIdx.x; i < nt_in; i += 64) ti += a.bpart_in[i];
-    for (int i = threadIdx.x; i < nt_out; i += 64) to += a.bpart_out[i];
-    for (int i = threadIdx.x; i < nt01; i += 64) tn += a.spart[i];
-    ti = wave_sum(ti);
-    to = wave_sum(to);
-    tn = wave_sum(tn);
+    for (int i = threadIdx.x; i < nt_in; i += FIN_BLOCK) ti += a.bpart_in[i];
+    for (int i = threadIdx.x; i < nt_out; i += FIN_BLOCK) to += a.bpart_out[i];
+    for (int i = threadIdx.x; i < nt01; i += FIN_BLOCK) tn += a.spart[i];
+    ti = block_sum<FIN_BLOCK>(ti, lds);
+    to = block_sum<FIN_BLOCK>(to, lds);
+    tn = block_sum<FIN_BLOCK>(tn, lds);
     if (threadIdx.x == 0) {
         DevState *st = a.st;
         const int64_t t = st->step;
@@ -645,7 +648,7 @@ __device__ __forceinline__ void finalize_step(const StepArgs &a, const int rd)
     }
 }
 
-__global__ __launch_bounds__(64) void k_step_finalize(StepArgs a)
+__global__ __launch_bounds__(FIN_BLOCK) void k_step_finalize(StepArgs a)
 {
     finalize_step(a, a.rd);
 }
@@ -996,8 +999,8 @@ __global__ __launch_bounds__(SC_BLOCK, 8) void k_batch_tile8(const BatchSample *
     batch_tile_body<T, OBS, BUF, MRT>(tab, work, parity);
 }
 
-// End of a batched step: one wave per sample, as k_step_finalize.
-__global__ __launch_bounds__(64) void k_batch_finalize(const BatchSample *__restrict__ tab, int32_t parity)
+// End of a batched step: one block per sample, as k_step_finalize.
+__global__ __launch_bounds__(FIN_BLOCK) void k_batch_finalize(const BatchSample *__restrict__ tab, int32_t parity)
 {
     const StepArgs a = tab[blockIdx.x].a;
     finalize_step(a, a.rd ^ parity);
