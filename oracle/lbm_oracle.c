@@ -705,6 +705,8 @@ typedef struct orc_colour {
     double *uz_in, *uz_out;  /* [ny][nx] boundary velocities */
 } orc_colour;
 
+void orc_colour_destroy(orc_colour *C);
+
 orc_colour *orc_colour_create(int nx, int ny, int nz, const unsigned char *solid, int periodic_x,
                               int periodic_y, int z_mode, double tau, double rho0,
                               double q_target, double rho_out, double alpha, double beta,
@@ -735,7 +737,8 @@ orc_colour *orc_colour_create(int nx, int ny, int nz, const unsigned char *solid
     C->uz_out = (double *)calloc((size_t)nx * ny, sizeof(double));
     if (!C->A || !C->B || !C->At || !C->Bt || !C->na || !C->nb || !C->phi || !C->uz_in ||
         !C->uz_out) {
-        /* leave cleanup to the caller's destroy */
+        orc_colour_destroy(C); /* frees whatever was allocated, and the lattice */
+        return NULL;
     }
     return C;
 }
@@ -787,9 +790,10 @@ void orc_colour_get_state(const orc_colour *C, double *f, double *A, double *B)
     memcpy(B, C->B, (size_t)C->L->ncell * Q7 * sizeof(double));
 }
 
-/* phi of the neighbour x + xi_q of pore cell (x, y, z), with the readings
- * above for solids, sides and the open z faces. */
-static double neighbour_phi(const orc_colour *C, int x, int y, int z, int q)
+/* phi of the neighbour x + xi_q of pore cell (x, y, z) in the dense phase
+ * field phi, with the readings above for solids, sides and the open z
+ * faces. */
+static double neighbour_phi(const orc_colour *C, const double *phi, int x, int y, int z, int q)
 {
     const orc_lattice *L = C->L;
     int tx = x + CX[q], ty = y + CY[q], tz = z + CZ[q];
@@ -799,7 +803,7 @@ static double neighbour_phi(const orc_colour *C, int x, int y, int z, int q)
         else if (L->z_mode == ORC_Z_WALL)
             return C->phi_solid;
         else
-            return C->phi[cell_index(L, x, y, z)];
+            return phi[cell_index(L, x, y, z)];
     }
     if (tx < 0 || tx >= L->nx) {
         if (!L->periodic_x) return C->phi_solid;
@@ -810,7 +814,42 @@ static double neighbour_phi(const orc_colour *C, int x, int y, int z, int q)
         ty = (ty + L->ny) % L->ny;
     }
     long t = cell_index(L, tx, ty, tz);
-    return L->solid[t] ? C->phi_solid : C->phi[t];
+    return L->solid[t] ? C->phi_solid : phi[t];
+}
+
+/* Colour gradient at pore cell (x, y, z) by the isotropic D3Q19 stencil
+ * C = 3 sum_q w_q xi_q phi(x + xi_q) (Appendix A names the gradient of the
+ * phase field but prints no stencil; this one is exact for fields up to
+ * quadratic order away from solids and faces). */
+static void colour_gradient_site(const orc_colour *C, const double *phi, int x, int y, int z,
+                                 double *gx, double *gy, double *gz)
+{
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int q = 1; q < Q19; ++q) {
+        const double p = neighbour_phi(C, phi, x, y, z, q);
+        ax += 3.0 * W[q] * CX[q] * p;
+        ay += 3.0 * W[q] * CY[q] * p;
+        az += 3.0 * W[q] * CZ[q] * p;
+    }
+    *gx = ax;
+    *gy = ay;
+    *gz = az;
+}
+
+/* The colour gradient of a given dense phase field phi [cell] at every pore
+ * cell, grad [cell][3] (zero at solid cells): the stencil the step uses. */
+void orc_colour_gradient(const orc_colour *C, const double *phi, double *grad)
+{
+    const orc_lattice *L = C->L;
+    for (int z = 0; z < L->nz; ++z)
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                long c = cell_index(L, x, y, z);
+                grad[c * 3] = grad[c * 3 + 1] = grad[c * 3 + 2] = 0.0;
+                if (L->solid[c]) continue;
+                colour_gradient_site(C, phi, x, y, z, &grad[c * 3], &grad[c * 3 + 1],
+                                     &grad[c * 3 + 2]);
+            }
 }
 
 /* One two-fluid step. hist (may be NULL): rho_in, Q_in, Q_out, mass, max|u|,
@@ -897,13 +936,8 @@ static int colour_step_once(orc_colour *C, double *hist)
             for (int x = 0; x < nx; ++x) {
                 long c = cell_index(L, x, y, z);
                 if (L->solid[c]) continue;
-                double gx = 0.0, gy = 0.0, gz = 0.0;
-                for (int q = 1; q < Q19; ++q) {
-                    const double p = neighbour_phi(C, x, y, z, q);
-                    gx += 3.0 * W[q] * CX[q] * p;
-                    gy += 3.0 * W[q] * CY[q] * p;
-                    gz += 3.0 * W[q] * CZ[q] * p;
-                }
+                double gx, gy, gz;
+                colour_gradient_site(C, C->phi, x, y, z, &gx, &gy, &gz);
                 double *f = &L->ft[c * Q19];
                 double rho, jx, jy, jz;
                 moments(f, &rho, &jx, &jy, &jz);

@@ -91,6 +91,7 @@ def _load():
         lib.orc_colour_step.restype = _i
         lib.orc_colour_fields.argtypes = [_p, _p, _p, _p, _p, _p]
         lib.orc_colour_set_collision.argtypes = [_p, _i]
+        lib.orc_colour_gradient.argtypes = [_p, _p, _p]
         _lib = lib
         return lib
 
@@ -309,6 +310,17 @@ class OracleColour:
         arrs = [np.empty(self.shape, np.float64) for _ in range(5)]
         self._lib.orc_colour_fields(self._h, *[_ptr(a) for a in arrs])
         return tuple(arrs)
+
+    def gradient(self, phi: np.ndarray) -> np.ndarray:
+        """Colour gradient (nz, ny, nx, 3) of a dense phase field phi (nz, ny, nx)
+        by the stencil the step uses (solid neighbours read phi_solid; zero at
+        solid cells)."""
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        if phi.shape != self.shape:
+            raise ValueError("phi must be (nz, ny, nx)")
+        out = np.empty(self.shape + (3,), np.float64)
+        self._lib.orc_colour_gradient(self._h, _ptr(phi), _ptr(out))
+        return out
 
     def step(self, n: int = 1, record: bool = True):
         hist = np.empty((n, 7), np.float64) if record else None
