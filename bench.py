@@ -12,9 +12,19 @@ the same workload, and the learned controller's steps-to-tolerance against
 the plain update on a held-out 128^3 pack.
 
 Other workloads (``--config``): pack256h (FP16 deviation storage), pack256m
-(MRT collision), pack512 (512^3, porosity 0.25), slit (FP64 16x16x64) and
-batch64 (64 samples of uneven size in one batched launch per step, with the
+(MRT collision), pack512 (512^3, porosity 0.25), slit (FP64 16x16x64),
+pack384c / pack384ch (the two-fluid colour model on the 384^3 pack, FP32 /
+FP16 deviations), pack256c (the colour model on the 256^3 pack) and batch64
+(64 samples of uneven size in one batched launch per step, with the
 autotuned schedule).
+
+The roofline object carries two byte counts per site: ``bytes_per_lup``,
+what this design's step kernels must move (the compact pull table, the
+colour model's two passes), and ``bytes_per_lup_survey``, the plain count of
+19 populations read and written once plus 18 int32 indices (224 B FP32,
+148 B FP16 deviations, 376 B FP64; the colour model adds its two D3Q7
+colours and the phase field: 340 B FP32, 208 B FP16), with ``frac`` and
+``frac_survey`` the achieved fractions of 8 TB/s under each.
 """
 from __future__ import annotations
 
@@ -31,6 +41,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in ("kernels.h", "engine.hip", "pull_format.h")]
+COLOUR_SOURCES = KERNEL_SOURCES + [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", "colour.h")]
+
+# Two-fluid pack workload: interfacial tension gamma = 0.01, reached at
+# alpha = 0.0156616 (the Laplace law of cylindrical drops on the FP64 oracle,
+# tests/golden/colour_calibration.json, written by
+# tests/golden/make_colour_calibration.py); contact angle 45 deg through
+# phi_solid = -cos(45 deg); unit viscosity ratio (tau = 1, mu = rho0 nu =
+# 1/6); capillary number Ca = mu Q* / (gamma eps A) = 1e-5 over the
+# 384^2 inlet at porosity eps = 0.30.
+ALPHA_GAMMA_001 = 0.0156616
+Q_CA_384 = 1e-5 * 0.01 * 0.30 * 384 * 384 / (1.0 / 6.0)
 
 CONFIGS = {
     # name: (builder, lattice kwargs, description)
@@ -42,6 +63,11 @@ CONFIGS = {
     # two-fluid colour model: non-wetting fluid in the inlet reservoir, wetting elsewhere
     "pack256c": dict(n=256, porosity=0.35, seed=2, reservoir=6, tau=0.8, darcy=1e-4, precision="fp32",
                      model="colour", alpha=0.005, beta=0.7, phi_solid=-0.5),
+    # the two-fluid configuration: 384^3 pack, porosity 0.30, gamma 0.01, 45 deg, Ca 1e-5
+    "pack384c": dict(n=384, porosity=0.30, seed=3, reservoir=6, tau=1.0, q=Q_CA_384, precision="fp32",
+                     model="colour", alpha=ALPHA_GAMMA_001, beta=0.7, phi_solid=-0.7071),
+    "pack384ch": dict(n=384, porosity=0.30, seed=3, reservoir=6, tau=1.0, q=Q_CA_384, precision="fp16dev",
+                      model="colour", alpha=ALPHA_GAMMA_001, beta=0.7, phi_solid=-0.7071),
     "slit": dict(slit=True, tau=1.0, q=0.5, precision="fp64"),
     # 64 samples of uneven size in one batched launch per step
     "batch64": dict(batch=64, seed=3, edge=(64, 192), porosity=(0.2, 0.45), darcy=(1e-5, 1e-3),
@@ -51,20 +77,34 @@ SCHEDULE_CACHE = os.path.join(ROOT, "paper_1806_10589_amd", "schedule_cache.txt"
 
 
 def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share16: float = 0.0) -> float:
-    """Algorithmic bytes of one pore-site update: 19 populations read and
-    written once in the storage type, plus the pull table: 18 int32 indices,
-    or, on the shares of tiles that read compact codes, 18 8-bit or 16-bit
-    codes and the tile's 80-byte header over its 512 sites. The colour model
-    (int32 table) adds, per site, the phase pass (14 D3Q7 colour values
-    read, 6 indices, N_A, N_B and phi written) and, in the colour step, phi
-    of the 18 neighbours, N_A, N_B and the 14 recoloured values written."""
+    """Algorithmic bytes of one pore-site update in this design: 19
+    populations read and written once in the storage type, plus the pull
+    table: 18 int32 indices, or, on the shares of tiles that read compact
+    codes, 18 8-bit or 16-bit codes and the tile's 80-byte header over its
+    512 sites. The colour model adds, per site: in the phase pass the 7
+    colour pairs (A_q, B_q) read (6 of them pulled, with the codes of
+    directions 1-6: 2 words of byte codes, 3 of 16-bit codes or 6 int32) and
+    N_A + N_B and phi written; in the colour step phi (the neighbours' values
+    counted once) and N_A + N_B read and the 7 recoloured pairs written. The
+    colours are FP64 in FP64 storage and FP32 otherwise."""
     elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
     hdr = 80 / 512
     table = 18 * 4 * (1.0 - share8 - share16) + (18 + hdr) * share8 + (36 + hdr) * share16
     single = 19 * 2 * elem + table
     if model != "colour":
         return single
-    return single + (14 * elem + 6 * 4 + 3 * elem) + (18 * elem + 2 * elem + 14 * elem)
+    ce = 8 if precision == "fp64" else 4
+    table6 = 6 * 4 * (1.0 - share8 - share16) + (8 + hdr) * share8 + (12 + hdr) * share16
+    return single + (14 * ce + table6 + 2 * ce) + (2 * ce + 14 * ce)
+
+
+def bytes_per_lup_survey(precision: str, model: str = "bgk") -> float:
+    """The plain byte count per site: 19 populations read and written once
+    and 18 int32 pull indices; the colour model adds its two D3Q7 colours
+    read and written once in the storage type and the phase field once."""
+    elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
+    single = 19 * 2 * elem + 72
+    return single if model != "colour" else single + 14 * 2 * elem + 4
 
 
 def pull_share(lats, fmt: str):
@@ -85,22 +125,23 @@ def pull_share(lats, fmt: str):
     return (t8 / tiles, t16 / tiles) if tiles else (0.0, 0.0)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(colour: bool = False) -> str:
     import hashlib
 
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
+    for path in (COLOUR_SOURCES if colour else KERNEL_SOURCES):
         with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str, n_sites: int, pull: str = "compact"):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
+def measured_traffic(workload: str, precision: str, n_sites: int, pull: str = "compact", colour: bool = False):
+    """HBM bytes per step of the step kernel(s) from the committed rocprofv3
     counter summary of this workload, or None when there is none, it was
     taken with another pull-table format, or the kernel sources changed
     since the counters were taken."""
-    path = os.path.join(PROFILE_DIR, f"k_stream_collide_{workload}_{precision}.md")
+    name = f"k_colour_{workload}_{precision}.md" if colour else f"k_stream_collide_{workload}_{precision}.md"
+    path = os.path.join(PROFILE_DIR, name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -109,7 +150,7 @@ def measured_traffic(workload: str, precision: str, n_sites: int, pull: str = "c
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or vals.get("pull_table", "int32") != pull:
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash(colour) or vals.get("pull_table", "int32") != pull:
         return None
     try:
         per_site = float(vals["hbm_bytes_per_site"])
@@ -127,7 +168,7 @@ def make_workload(cfg):
                           periodic_x=False, periodic_y=True), {"porosity": float((mask == 0).mean())}
     mask, phi, nsph = inputs.sphere_pack(cfg["n"], cfg["porosity"], seed=cfg["seed"],
                                          reservoir_layers=cfg["reservoir"])
-    q = cfg["darcy"] * mask.shape[1] * mask.shape[2]
+    q = cfg["q"] if "q" in cfg else cfg["darcy"] * mask.shape[1] * mask.shape[2]
     kw = dict(tau=cfg["tau"], q_target=q, precision=cfg["precision"], periodic_x=True, periodic_y=True,
               model=cfg.get("model", "bgk"))
     for k in ("alpha", "beta", "phi_solid"):
@@ -198,7 +239,9 @@ def run_batch(args, cfg):
     torch.cuda.synchronize()
     ms_seq = e0.elapsed_time(e1) / k_seq
     bpl = bytes_per_lup(cfg["precision"], "bgk", *share)
+    bpl_s = bytes_per_lup_survey(cfg["precision"], "bgk")
     achieved = n_total * bpl / (ms_kernel * 1e-3) / 1e9
+    achieved_s = n_total * bpl_s / (ms_kernel * 1e-3) / 1e9
     out = {
         "metric": "MLUPS (pore sites) + HBM GB/s; steps-to-flux-tol, learned vs plain",
         "value": round(mlups, 1),
@@ -235,6 +278,9 @@ def run_batch(args, cfg):
             "kernel": "k_batch_step",
             "kernel_ms": round(ms_kernel, 5),
             "bytes_per_lup": round(bpl, 2),
+            "bytes_per_lup_survey": round(bpl_s, 2),
+            "achieved_survey": round(achieved_s, 1),
+            "frac_survey": round(achieved_s / HBM_PEAK_GBS, 4),
         },
     }
     m0, kw0, _ = samples[0]
@@ -283,10 +329,24 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(mask, kw, steps, reservoir=6):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(mask, kw, steps, reservoir=6, steps_t1=None):
     """FP64 oracle on the same workload, `steps` steps after one warm-up step
-    (the two-fluid oracle for the colour model, started from the same
-    two-layer colour state)."""
+    with every thread OpenMP offers, then `steps_t1` steps on one thread (the
+    two-fluid oracle for the colour model, started from the same two-layer
+    colour state)."""
     import numpy as np
 
     import oracle
@@ -308,21 +368,101 @@ def cpu_baseline(mask, kw, steps, reservoir=6):
                                    periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
         orc.set_mrt(kw.get("model") == "mrt")
         orc.init_equilibrium(1.0)
+    threads = oracle.oracle.max_threads()
     orc.step(1, record=False)
     t0 = time.perf_counter()
     orc.step(steps, record=False)
     dt = time.perf_counter() - t0
     n_pore = int((mask == 0).sum())
-    return {
+    out = {
         "value": n_pore * steps / dt / 1e6,
         "unit": "MLUPS",
-        "cores": oracle.oracle.max_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"{steps} steps of the full {mask.shape[2]}x{mask.shape[1]}x{mask.shape[0]} lattice "
-                  f"after 1 warm-up step ({dt:.1f} s); FP64 dense push-scheme "
+                  f"after 1 warm-up step ({dt:.1f} s) on {threads} threads; FP64 dense push-scheme "
                   f"{'two-fluid ' if colour else ''}oracle, OpenMP over z",
         "mlups_per_voxel": mask.size * steps / dt / 1e6,
+        "cpu_model": cpu_model(),
+        "logical_cpus": os.cpu_count(),
     }
+    if steps_t1:
+        oracle.oracle.set_threads(1)
+        try:
+            t0 = time.perf_counter()
+            orc.step(steps_t1, record=False)
+            dt1 = time.perf_counter() - t0
+        finally:
+            oracle.oracle.set_threads(threads)
+        out["value_1_thread"] = n_pore * steps_t1 / dt1 / 1e6
+        out["sample_1_thread"] = f"{steps_t1} steps on 1 thread ({dt1:.1f} s)"
+    return out
+
+
+def roofline_of(config, kw, n, share, ms_kernel, ms_plane, pull):
+    """The roofline object of a step: algorithmic bytes of this design and
+    the plain survey count, each over the kernels' mean HIP-event duration,
+    and the counter traffic of the committed profile when it is current."""
+    colour = kw.get("model") == "colour"
+    bpl = bytes_per_lup(kw["precision"], kw.get("model", "bgk"), *share)
+    bpl_s = bytes_per_lup_survey(kw["precision"], kw.get("model", "bgk"))
+    achieved = n * bpl / (ms_kernel * 1e-3) / 1e9
+    achieved_s = n * bpl_s / (ms_kernel * 1e-3) / 1e9
+    traffic = measured_traffic(config, kw["precision"], n, pull, colour=colour)
+    out = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "k_phase_buf+k_colour_buf" if colour else "k_stream_collide",
+        "kernel_ms": round(ms_kernel, 5),
+        "plane_kernel_ms": round(ms_plane, 5),
+        "bytes_per_lup": round(bpl, 2),
+        "bytes_per_lup_survey": round(bpl_s, 2),
+        "achieved_survey": round(achieved_s, 1),
+        "frac_survey": round(achieved_s / HBM_PEAK_GBS, 4),
+    }
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / (n * bpl), 4)
+        out["traffic_gbs"] = round(traffic / (ms_kernel * 1e-3) / 1e9, 1)
+    return out
+
+
+def pack512_line(args, steps=400, warmup=40):
+    """Throughput of the same step on the 512^3 pack (porosity 0.25, Darcy
+    velocity 1e-5, 35.5M pore sites, FP32, compact pull table): a short
+    graph-timed run and the step kernel's HIP-event duration."""
+    import torch
+
+    from paper_1806_10589_amd import fluxlbm
+
+    cfg = CONFIGS["pack512"]
+    mask, kw, info = make_workload(cfg)
+    lat = fluxlbm.Lattice(mask, watchdog_every=1000, **kw)
+    try:
+        share = pull_share([lat], args.pull)
+        lat.init_equilibrium(1.0)
+        lat.step(warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ok = lat.sync() == fluxlbm.FLBM_OK
+        ms_plane, ms_kernel = lat.profile_kernels(50)
+        n = lat.n_sites
+        return {"workload": "pack512", "pore_sites": n, "steps": steps, "ms_per_step": round(ms, 5),
+                "mlups": round(n / (ms * 1e-3) / 1e6, 1), "status": "ok" if ok else "unstable",
+                "porosity": info["porosity"],
+                "roofline": roofline_of("pack512", kw, n, share, ms_kernel, ms_plane, args.pull)}
+    finally:
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
 
 
 def main():
@@ -333,12 +473,14 @@ def main():
     ap.add_argument("--config", default="pack256", choices=sorted(CONFIGS))
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--cpu-steps", type=int, default=150)
+    ap.add_argument("--cpu-steps-1-thread", type=int, default=10,
+                    help="steps of the oracle timed on one thread after the multi-threaded sample (0: none)")
+    ap.add_argument("--no-pack512", action="store_true", help="leave out the 512^3 throughput key")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-controller", action="store_true")
     ap.add_argument("--pull", choices=["compact", "half", "int32"], default="compact",
-                    help="pull-table format of the single-fluid step: 8/16-bit codes, 16-bit codes, or the "
-                         "int32 table (colour: int32 always)")
+                    help="pull-table format of the step: 8/16-bit codes, 16-bit codes, or the int32 table")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -357,7 +499,8 @@ def main():
     print(f"[bench] workload {args.config}: mask {mask.shape}, pore sites {(mask == 0).sum()}",
           file=sys.stderr, flush=True)
     lat = fluxlbm.Lattice(mask, watchdog_every=1000, **kw)
-    share = pull_share([lat], args.pull) if kw.get("model") != "colour" else (0.0, 0.0)
+    colour = kw.get("model") == "colour"
+    share = pull_share([lat], args.pull)
     if kw.get("model") == "colour":
         z = lat.coords()[:, 2]
         na = (z < cfg["reservoir"]).astype(float)
@@ -388,20 +531,7 @@ def main():
 
     # per-kernel durations with HIP events on the launch stream
     ms_plane, ms_kernel = lat.profile_kernels(args.profile_steps)
-    bpl = bytes_per_lup(kw["precision"], kw.get("model", "bgk"), *share)
-    achieved = n * bpl / (ms_kernel * 1e-3) / 1e9
-    roofline = {
-        "bound": "hbm",
-        "achieved": round(achieved, 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(args.config, kw["precision"], n, args.pull),
-        "kernel": "k_phase+k_colour" if kw.get("model") == "colour" else "k_stream_collide",
-        "kernel_ms": round(ms_kernel, 5),
-        "plane_kernel_ms": round(ms_plane, 5),
-        "bytes_per_lup": round(bpl, 2),
-    }
+    roofline = roofline_of(args.config, kw, n, share, ms_kernel, ms_plane, args.pull)
     out = {
         "metric": "MLUPS (pore sites) + HBM GB/s; steps-to-flux-tol, learned vs plain",
         "value": round(mlups, 1),
@@ -424,11 +554,11 @@ def main():
             "q_target": kw["q_target"],
             "precision": kw["precision"],
             "collision": kw.get("model", "bgk"),
-            "pull_table": "int32" if kw.get("model") == "colour" else args.pull,
+            "pull_table": args.pull,
             "tile_share_8bit_16bit": [round(v, 4) for v in share],
             **info,
         },
-        "hbm_gbs_model": round(mlups * bpl / 1e3, 1),
+        "hbm_gbs_model": round(mlups * roofline["bytes_per_lup"] / 1e3, 1),
         "status": "ok" if status == fluxlbm.FLBM_OK else "unstable",
         "roofline": roofline,
     }
@@ -437,10 +567,12 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_gbs"] = round(copy_bandwidth(torch), 1)
+    if args.config == "pack256" and not args.no_pack512:
+        out["pack512"] = pack512_line(args)
     if not args.no_controller and args.config == "pack256":
         out["controller_ab"] = controller_ab()
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
-        out["cpu_baseline"] = cpu_baseline(mask, kw, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(mask, kw, args.cpu_steps, steps_t1=args.cpu_steps_1_thread)
     print(json.dumps(out), flush=True)
 
 

@@ -35,6 +35,10 @@
  *   - A context is not thread-safe; distinct contexts are independent.
  *   - Every call returns FLBM_OK (0) or a negative flbm_status; the text of
  *     the last error of a context is available from flbm_last_error.
+ *   - Testing aids read from the environment at flbm_create: FLBM_NO_GRAPH=1
+ *     launches every step directly instead of replaying captured graphs;
+ *     FLBM_NO_BUF=1 takes the 64-bit addressing path of lattices past 4 GiB
+ *     (no raw buffer instructions, no compact pull table) at any size.
  */
 #ifndef FLUXLBM_H
 #define FLUXLBM_H
@@ -374,9 +378,10 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
  *                      p + c, 0xFE the sentinel, 0xFF bounce-back: 18 bytes
  *                      per site.
  * A tile whose sources of some direction span more than a form's range
- * falls back to the next wider form, down to the int32 table. The colour
- * model, and lattices too large for the 4 GiB buffer path, have no compact
- * table (FLBM_ESTATE for the coded formats). limit16 (<= 0xFFFD) and limit8
+ * falls back to the next wider form, down to the int32 table. Both passes of
+ * the colour model read it too (the phase pass directions 1..6). Lattices
+ * too large for the 4 GiB buffer path have no compact table (FLBM_ESTATE for
+ * the coded formats). limit16 (<= 0xFFFD) and limit8
  * (<= 0xFD) below the defaults (0 means the default) are a testing aid that
  * sends more tiles to the wider forms. Synchronises; rebuilds the codes on
  * the host (O(18 n)) when a limit changes. */

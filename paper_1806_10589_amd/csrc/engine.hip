@@ -68,7 +68,7 @@ struct flbm_ctx {
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
     int32_t *nbr = nullptr;
-    // compact pull table (single-fluid model on the buffer path)
+    // compact pull table (buffer path)
     CompactPull pull;
     int pull_format = FLBM_PULL_INT32;
     uint32_t *pull_codes = nullptr, *pull_bytes = nullptr;
@@ -83,8 +83,9 @@ struct flbm_ctx {
     double *fields = nullptr;
     // two-fluid colour model
     bool colour = false;
-    void *ca[2] = {nullptr, nullptr}, *cb[2] = {nullptr, nullptr};  // [7][n_pad] each
-    void *na = nullptr, *nb = nullptr, *phi = nullptr;              // [n_pad] each
+    void *cab[2] = {nullptr, nullptr};  // colour pairs (A_q, B_q) [7][n_pad]
+    void *nab = nullptr;                // (N_A, N_B) pairs [n_pad]
+    void *phi = nullptr;                // phase field [n_pad]
     double *obs_na = nullptr, *obs_nb = nullptr;
     // learned inlet controller
     bool ctrl_on = false;
@@ -196,11 +197,12 @@ size_t carve(flbm_ctx *c, char *base)
     char *cf = take(16 * sizeof(float));
     char *ct = take((size_t)HIST_CAP * 40 * sizeof(float));
     char *cr = take(256 * sizeof(double));
-    char *cc[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    char *cc[4] = {nullptr, nullptr, nullptr, nullptr};
     char *on = nullptr, *ob2 = nullptr;
     if (c->colour) {
-        for (int i = 0; i < 4; ++i) cc[i] = take((size_t)7 * npad * colour_elem(c));
-        for (int i = 4; i < 7; ++i) cc[i] = take((size_t)npad * colour_elem(c));
+        for (int i = 0; i < 2; ++i) cc[i] = take((size_t)7 * npad * 2 * colour_elem(c));
+        cc[2] = take((size_t)npad * 2 * colour_elem(c));
+        cc[3] = take((size_t)npad * colour_elem(c));
         on = take((size_t)c->obs_slots * sizeof(double));
         ob2 = take((size_t)c->obs_slots * sizeof(double));
     }
@@ -226,13 +228,10 @@ size_t carve(flbm_ctx *c, char *base)
         c->ctrl_trace = (float *)ct;
         c->ctrl_ring = (double *)cr;
         if (c->colour) {
-            c->ca[0] = cc[0];
-            c->ca[1] = cc[1];
-            c->cb[0] = cc[2];
-            c->cb[1] = cc[3];
-            c->na = cc[4];
-            c->nb = cc[5];
-            c->phi = cc[6];
+            c->cab[0] = cc[0];
+            c->cab[1] = cc[1];
+            c->nab = cc[2];
+            c->phi = cc[3];
             c->obs_na = (double *)on;
             c->obs_nb = (double *)ob2;
         }
@@ -325,32 +324,37 @@ void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
     p.st = c->st;
     p.nbr = c->nbr;
     p.fin = c->f[from];
-    p.ain = c->ca[from];
-    p.bin = c->cb[from];
-    p.aout = c->ca[from ^ 1];
-    p.bout = c->cb[from ^ 1];
-    p.na = c->na;
-    p.nb = c->nb;
+    p.abin = c->cab[from];
+    p.about = c->cab[from ^ 1];
+    p.nab = c->nab;
     p.phi = c->phi;
-    hipLaunchKernelGGL(k_phase<T>, dim3(c->blocks256), dim3(BLOCK), 0, s, p);
     StepArgs a = step_args(c);
     a.rd = from;
+    if (c->use_buf)
+        hipLaunchKernelGGL(k_phase_buf<T>, dim3(c->tiles), dim3(TILE / PHASE_V), 0, s, p, a);
+    else
+        hipLaunchKernelGGL(k_phase<T>, dim3(c->blocks256), dim3(BLOCK), 0, s, p);
     ColourStepArgs cs{};
     cs.alpha = c->p.alpha;
     cs.beta = c->p.beta;
     cs.phi_solid = c->p.phi_solid;
     cs.sentinel = c->lat.sentinel;
-    cs.na = c->na;
-    cs.nb = c->nb;
+    cs.nab = c->nab;
     cs.phi = c->phi;
-    cs.aout = c->ca[from ^ 1];
-    cs.bout = c->cb[from ^ 1];
+    cs.about = c->cab[from ^ 1];
     const T *fin = (const T *)c->f[from];
     T *fout = (T *)c->f[from ^ 1];
-    if (obs)
+    if (c->use_buf) {
+        const dim3 grid(c->tiles);
+        if (obs)
+            hipLaunchKernelGGL((k_colour_buf<T, true>), grid, dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
+        else
+            hipLaunchKernelGGL((k_colour_buf<T, false>), grid, dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
+    } else if (obs) {
         hipLaunchKernelGGL((k_colour<T, true>), dim3(c->tiles), dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
-    else
+    } else {
         hipLaunchKernelGGL((k_colour<T, false>), dim3(c->tiles), dim3(TILE), 0, s, fin, fout, c->nbr, a, cs);
+    }
 }
 
 // The fused kernel in its variants: with or without the watchdog partials;
@@ -657,10 +661,9 @@ flbm_status setup_device(flbm_ctx *c, void *mem)
                                  hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemsetAsync(c->kpart, 0, PLANE_MAX_BLOCKS * sizeof(double), c->stream));
     if (c->colour) {
-        for (int i = 0; i < 2; ++i) {
-            HIPCHK(c, hipMemsetAsync(c->ca[i], 0, (size_t)7 * c->lat.n_pad * colour_elem(c), c->stream));
-            HIPCHK(c, hipMemsetAsync(c->cb[i], 0, (size_t)7 * c->lat.n_pad * colour_elem(c), c->stream));
-        }
+        for (int i = 0; i < 2; ++i)
+            HIPCHK(c, hipMemsetAsync(c->cab[i], 0, (size_t)14 * c->lat.n_pad * colour_elem(c), c->stream));
+        HIPCHK(c, hipMemsetAsync(c->nab, 0, (size_t)2 * c->lat.n_pad * colour_elem(c), c->stream));
         HIPCHK(c, hipMemsetAsync(c->phi, 0, (size_t)c->lat.n_pad * colour_elem(c), c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -760,8 +763,13 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
     }
     c->tiles = (int)(c->lat.n_pad / TILE);
     c->use_buf = f_bytes(c) < (1ull << 32) && (uint64_t)18 * c->lat.n_pad * 4 < (1ull << 32);
-    if (!c->colour && c->use_buf) {
-        // the single-fluid step reads the compact pull table where it fits
+    // testing aid: FLBM_NO_BUF=1 takes the 64-bit addressing path (that of
+    // lattices past 4 GiB) for a context of any size
+    const char *nobuf = std::getenv("FLBM_NO_BUF");
+    if (nobuf && nobuf[0] == '1') c->use_buf = false;
+    if (c->use_buf) {
+        // the step (and both passes of the colour step) reads the compact pull
+        // table where it fits
         e = build_compact_pull(c->lat, TILE, (int32_t)PULL_MAX_CODE, (int32_t)PULL_MAX_BYTE, c->pull);
         if (!e.empty()) {
             delete c;
@@ -950,7 +958,7 @@ flbm_status flbm_set_pull_format(flbm_ctx *c, int32_t format, int32_t limit16, i
     if (limit16 < 0 || (uint32_t)limit16 > PULL_MAX_CODE || limit8 < 0 || (uint32_t)limit8 > PULL_MAX_BYTE)
         return fail(c, FLBM_EINVAL, "code limit out of range");
     if (format != FLBM_PULL_INT32 && !c->pull.tiles)
-        return fail(c, FLBM_ESTATE, "no compact pull table (colour model, or a lattice past the 4 GiB buffer path)");
+        return fail(c, FLBM_ESTATE, "no compact pull table (a lattice past the 4 GiB buffer path)");
     const int32_t l16 = limit16 ? limit16 : (int32_t)PULL_MAX_CODE;
     const int32_t l8 = format == FLBM_PULL_COMPACT ? (limit8 ? limit8 : (int32_t)PULL_MAX_BYTE) : 0;
     if (c->ready) {
@@ -997,7 +1005,8 @@ flbm_status flbm_get_compact_pull(const flbm_ctx *c, uint32_t *codes16, uint32_t
     return FLBM_OK;
 }
 
-// Distributions in a checkpoint: f, then A and B for the colour model.
+// Distributions in a checkpoint: f, then the colour pairs (A_q, B_q) for the
+// colour model.
 static size_t state_f_bytes(const flbm_ctx *c)
 {
     return (size_t)19 * c->lat.n_pad * c->elem + (c->colour ? (size_t)14 * c->lat.n_pad * colour_elem(c) : 0);
@@ -1028,9 +1037,8 @@ flbm_status flbm_save_state(flbm_ctx *c, void *host, size_t bytes)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(host, c->f[c->cur], f19, hipMemcpyDeviceToHost));
     if (c->colour) {
-        const size_t c7 = (size_t)7 * c->lat.n_pad * colour_elem(c);
-        HIPCHK(c, hipMemcpy((char *)host + f19, c->ca[c->cur], c7, hipMemcpyDeviceToHost));
-        HIPCHK(c, hipMemcpy((char *)host + f19 + c7, c->cb[c->cur], c7, hipMemcpyDeviceToHost));
+        const size_t c14 = (size_t)14 * c->lat.n_pad * colour_elem(c);
+        HIPCHK(c, hipMemcpy((char *)host + f19, c->cab[c->cur], c14, hipMemcpyDeviceToHost));
     }
     DevState d{};
     HIPCHK(c, hipMemcpy(&d, c->st, sizeof(d), hipMemcpyDeviceToHost));
@@ -1049,9 +1057,8 @@ flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(c->f[c->cur], host, f19, hipMemcpyHostToDevice));
     if (c->colour) {
-        const size_t c7 = (size_t)7 * c->lat.n_pad * colour_elem(c);
-        HIPCHK(c, hipMemcpy(c->ca[c->cur], (const char *)host + f19, c7, hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(c->cb[c->cur], (const char *)host + f19 + c7, c7, hipMemcpyHostToDevice));
+        const size_t c14 = (size_t)14 * c->lat.n_pad * colour_elem(c);
+        HIPCHK(c, hipMemcpy(c->cab[c->cur], (const char *)host + f19, c14, hipMemcpyHostToDevice));
     }
     rc = reset_state(c);
     if (rc) return rc;
@@ -1068,39 +1075,46 @@ flbm_status flbm_load_state(flbm_ctx *c, const void *host, size_t bytes)
     return FLBM_OK;
 }
 
-// Host [7][n] FP64 colour distributions <-> device [7][n_pad] storage.
-static flbm_status write_colour_buffer(flbm_ctx *c, void *dst, const double *src)
+// Host [7][n] FP64 colour distributions A and B <-> device pairs (A_q, B_q)
+// [7][n_pad] in the colour storage type.
+extern "C++" {
+template <typename C>
+static flbm_status write_colour_pairs_t(flbm_ctx *c, void *dst, const double *A, const double *B)
 {
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
-    if (is_fp64(c)) {
-        std::vector<double> h((size_t)7 * npad, 0.0);
-        for (int q = 0; q < 7; ++q)
-            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = src[q * n + s];
-        HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
-    } else {
-        std::vector<float> h((size_t)7 * npad, 0.0f);
-        for (int q = 0; q < 7; ++q)
-            for (int64_t s = 0; s < n; ++s) h[q * npad + s] = (float)src[q * n + s];
-        HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
-    }
+    std::vector<C> h((size_t)14 * npad, (C)0);
+    for (int q = 0; q < 7; ++q)
+        for (int64_t s = 0; s < n; ++s) {
+            h[2 * (q * npad + s)] = (C)A[q * n + s];
+            h[2 * (q * npad + s) + 1] = (C)B[q * n + s];
+        }
+    HIPCHK(c, hipMemcpy(dst, h.data(), h.size() * sizeof(C), hipMemcpyHostToDevice));
     return FLBM_OK;
 }
 
-static flbm_status read_colour_buffer(flbm_ctx *c, const void *src, double *dst)
+template <typename C>
+static flbm_status read_colour_pairs_t(flbm_ctx *c, const void *src, double *A, double *B)
 {
     const int64_t n = c->lat.n, npad = c->lat.n_pad;
-    if (is_fp64(c)) {
-        std::vector<double> h((size_t)7 * npad);
-        HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (int q = 0; q < 7; ++q)
-            for (int64_t s = 0; s < n; ++s) dst[q * n + s] = h[q * npad + s];
-    } else {
-        std::vector<float> h((size_t)7 * npad);
-        HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(float), hipMemcpyDeviceToHost));
-        for (int q = 0; q < 7; ++q)
-            for (int64_t s = 0; s < n; ++s) dst[q * n + s] = (double)h[q * npad + s];
-    }
+    std::vector<C> h((size_t)14 * npad);
+    HIPCHK(c, hipMemcpy(h.data(), src, h.size() * sizeof(C), hipMemcpyDeviceToHost));
+    for (int q = 0; q < 7; ++q)
+        for (int64_t s = 0; s < n; ++s) {
+            A[q * n + s] = (double)h[2 * (q * npad + s)];
+            B[q * n + s] = (double)h[2 * (q * npad + s) + 1];
+        }
     return FLBM_OK;
+}
+}  // extern "C++"
+
+static flbm_status write_colour_pairs(flbm_ctx *c, void *dst, const double *A, const double *B)
+{
+    return is_fp64(c) ? write_colour_pairs_t<double>(c, dst, A, B) : write_colour_pairs_t<float>(c, dst, A, B);
+}
+
+static flbm_status read_colour_pairs(flbm_ctx *c, const void *src, double *A, double *B)
+{
+    return is_fp64(c) ? read_colour_pairs_t<double>(c, src, A, B) : read_colour_pairs_t<float>(c, src, A, B);
 }
 
 flbm_status flbm_init_colour(flbm_ctx *c, const double *na, const double *nb)
@@ -1118,9 +1132,7 @@ flbm_status flbm_init_colour(flbm_ctx *c, const double *na, const double *nb)
             a[q * n + s] = d3q19::weight7(q) * na[s];
             b[q * n + s] = d3q19::weight7(q) * nb[s];
         }
-    rc = write_colour_buffer(c, c->ca[c->cur], a.data());
-    if (rc) return rc;
-    return write_colour_buffer(c, c->cb[c->cur], b.data());
+    return write_colour_pairs(c, c->cab[c->cur], a.data(), b.data());
 }
 
 flbm_status flbm_read_colour(flbm_ctx *c, double *A, double *B)
@@ -1130,9 +1142,7 @@ flbm_status flbm_read_colour(flbm_ctx *c, double *A, double *B)
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    rc = read_colour_buffer(c, c->ca[c->cur], A);
-    if (rc) return rc;
-    return read_colour_buffer(c, c->cb[c->cur], B);
+    return read_colour_pairs(c, c->cab[c->cur], A, B);
 }
 
 flbm_status flbm_write_colour(flbm_ctx *c, const double *A, const double *B)
@@ -1142,9 +1152,7 @@ flbm_status flbm_write_colour(flbm_ctx *c, const double *A, const double *B)
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    rc = write_colour_buffer(c, c->ca[c->cur], A);
-    if (rc) return rc;
-    rc = write_colour_buffer(c, c->cb[c->cur], B);
+    rc = write_colour_pairs(c, c->cab[c->cur], A, B);
     if (rc) return rc;
     return reset_state(c);
 }
@@ -1157,12 +1165,10 @@ flbm_status flbm_read_phase(flbm_ctx *c, double *phi)
     if (rc) return rc;
     if (is_fp64(c))
         hipLaunchKernelGGL(k_phase_of_state<double>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
-                           (const double *)c->ca[c->cur], (const double *)c->cb[c->cur], c->lat.n, c->lat.n_pad,
-                           c->fields);
+                           (const Pair<double>::type *)c->cab[c->cur], c->lat.n, c->lat.n_pad, c->fields);
     else
         hipLaunchKernelGGL(k_phase_of_state<float>, dim3(c->blocks256), dim3(BLOCK), 0, c->stream,
-                           (const float *)c->ca[c->cur], (const float *)c->cb[c->cur], c->lat.n, c->lat.n_pad,
-                           c->fields);
+                           (const Pair<float>::type *)c->cab[c->cur], c->lat.n, c->lat.n_pad, c->fields);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(phi, c->fields, c->lat.n * sizeof(double), hipMemcpyDeviceToHost));

@@ -281,9 +281,26 @@ def test_compact_pull_table_falls_back_per_tile():
         fluxlbm.flbm_destroy(ctx)
 
 
-def test_colour_model_has_no_compact_pull_table():
+def test_colour_model_reads_the_compact_pull_table():
     mask = inputs.random_mask((6, 8, 8), 0.2, 5)
     mask[0] = 0
+    ctx = fluxlbm.flbm_create(mask, _params(mask, model=fluxlbm.FLBM_COLOUR))
+    try:
+        fmt, t8, t16, tiles = fluxlbm.flbm_pull_format_info(ctx)
+        assert fmt == fluxlbm.FLBM_PULL_COMPACT and t8 + t16 <= tiles and tiles >= 1
+        for fmt in (fluxlbm.FLBM_PULL_HALF, fluxlbm.FLBM_PULL_INT32, fluxlbm.FLBM_PULL_COMPACT):
+            fluxlbm.flbm_set_pull_format(ctx, fmt)
+            assert fluxlbm.flbm_pull_format_info(ctx)[0] == fmt
+    finally:
+        fluxlbm.flbm_destroy(ctx)
+
+
+def test_no_buffer_path_has_no_compact_pull_table(monkeypatch):
+    """FLBM_NO_BUF=1 (testing aid) takes the 64-bit addressing path of
+    lattices past 4 GiB, which reads the int32 table only."""
+    mask = inputs.random_mask((6, 8, 8), 0.2, 5)
+    mask[0] = 0
+    monkeypatch.setenv("FLBM_NO_BUF", "1")
     ctx = fluxlbm.flbm_create(mask, _params(mask, model=fluxlbm.FLBM_COLOUR))
     try:
         assert fluxlbm.flbm_pull_format_info(ctx)[:3] == (fluxlbm.FLBM_PULL_INT32, 0, 0)

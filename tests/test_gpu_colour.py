@@ -2,6 +2,9 @@
 
 Per step: FP64 storage <= 1e-12, FP32 <= 1e-6 of max |value| for f, A and B.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -17,10 +20,20 @@ W7 = np.array([1 / 3] + [1 / 9] * 6)
 
 
 def colour_pair(mask, *, precision, tau=0.9, alpha=0.01, beta=0.7, phi_solid=-0.5, q_target=0.0,
-                periodic_x=True, periodic_y=True, z_mode=0, watchdog_every=1000):
-    lat = fluxlbm.Lattice(mask, tau=tau, q_target=q_target, precision=precision, model="colour",
-                          periodic_x=periodic_x, periodic_y=periodic_y, z_mode=z_mode,
-                          alpha=alpha, beta=beta, phi_solid=phi_solid, watchdog_every=watchdog_every)
+                periodic_x=True, periodic_y=True, z_mode=0, watchdog_every=1000, nobuf=False):
+    """The GPU lattice and the oracle on the same mask; nobuf: the GPU lattice
+    takes the 64-bit addressing path of lattices past 4 GiB (testing aid)."""
+    old = os.environ.pop("FLBM_NO_BUF", None)
+    if nobuf:
+        os.environ["FLBM_NO_BUF"] = "1"
+    try:
+        lat = fluxlbm.Lattice(mask, tau=tau, q_target=q_target, precision=precision, model="colour",
+                              periodic_x=periodic_x, periodic_y=periodic_y, z_mode=z_mode,
+                              alpha=alpha, beta=beta, phi_solid=phi_solid, watchdog_every=watchdog_every)
+    finally:
+        os.environ.pop("FLBM_NO_BUF", None)
+        if old is not None:
+            os.environ["FLBM_NO_BUF"] = old
     orc = oracle.OracleColour(mask, tau=tau, alpha=alpha, beta=beta, phi_solid=phi_solid,
                               q_target=q_target, periodic_x=periodic_x, periodic_y=periodic_y,
                               z_mode=z_mode)
@@ -59,24 +72,26 @@ def compare(lat, orc, mask):
     return ef, ea, eb
 
 
+@pytest.mark.parametrize("nobuf", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("z_mode,px,py", [(1, 1, 1), (2, 0, 1)])
-def test_colour_one_step_closed_box(precision, z_mode, px, py):
+def test_colour_one_step_closed_box(precision, z_mode, px, py, nobuf):
     mask = inputs.random_mask((9, 11, 13), 0.25, 201)
-    lat, orc = colour_pair(mask, precision=precision, periodic_x=px, periodic_y=py, z_mode=z_mode)
+    lat, orc = colour_pair(mask, precision=precision, periodic_x=px, periodic_y=py, z_mode=z_mode, nobuf=nobuf)
     load_colour_state(lat, orc, mask, 202)
     lat.step(1)
     orc.step(1)
     assert max(compare(lat, orc, mask)) <= TOL[precision]
 
 
+@pytest.mark.parametrize("nobuf", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("shape,px,py", [((10, 12, 11), 1, 0), ((6, 5, 4), 1, 1), ((20, 34, 30), 1, 1)])
-def test_colour_one_step_flux_box(precision, shape, px, py):
+def test_colour_one_step_flux_box(precision, shape, px, py, nobuf):
     mask = inputs.random_mask(shape, 0.25, 211)
     mask[0, 0, 0] = 0
     lat, orc = colour_pair(mask, precision=precision, q_target=0.002 * shape[1] * shape[2],
-                           periodic_x=px, periodic_y=py)
+                           periodic_x=px, periodic_y=py, nobuf=nobuf)
     load_colour_state(lat, orc, mask, 212)
     lat.step(1)
     h_orc = orc.step(1)
@@ -175,6 +190,14 @@ def crop64():
     return crop
 
 
+def alpha_for_gamma_001():
+    """The interfacial-stress strength giving interfacial tension 0.01, from
+    the oracle's Laplace-law calibration (golden/colour_calibration.json)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "colour_calibration.json")
+    with open(path) as fh:
+        return json.load(fh)["alpha"]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_colour_crop64_parity(crop64, precision):
     """FP64 and FP32 to their per-step tolerances; the FP16-deviation mode
@@ -182,7 +205,8 @@ def test_colour_crop64_parity(crop64, precision):
     FP64 oracle after 1 and 100 steps."""
     mask = crop64
     gamma_ca = 1e-5 * 0.01 * 0.30 * 64 * 64 / (1.0 / 6.0)  # Q* = Ca gamma eps A / mu_w
-    lat, orc = colour_pair(mask, precision=precision, tau=1.0, alpha=0.01, beta=0.7,
+    # gamma = 0.01 (alpha from the oracle's Laplace-law calibration), 45 deg
+    lat, orc = colour_pair(mask, precision=precision, tau=1.0, alpha=alpha_for_gamma_001(), beta=0.7,
                            phi_solid=-0.7071, q_target=gamma_ca, watchdog_every=50)
     na = np.zeros(mask.shape)
     na[:6] = 1.0

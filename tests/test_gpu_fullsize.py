@@ -84,12 +84,12 @@ def test_colour_full_pack_properties():
     both faces -- the wetting colour leaves only through the outlet, at the
     fluid's outflow (B changes by -sum Q_out, to the density's deviation
     from one in the outlet's pressure wave)."""
-    from paper_1806_10589_amd import inputs
-    mask, phi, _ = inputs.sphere_pack(384, 0.30, seed=3, reservoir_layers=6)
-    print(f"colour full: mask {mask.shape}, porosity {phi:.3f}", flush=True)
-    q = 1e-5 * 0.01 * 0.30 * 384 * 384 / (1.0 / 6.0)   # Q* = Ca gamma eps A / mu_w, mu_w = 1/6
-    lat = fluxlbm.Lattice(mask, precision="fp32", model="colour", tau=1.0, alpha=0.01, beta=0.7,
-                          phi_solid=-0.7071, q_target=q, watchdog_every=10)
+    # the benchmark's two-fluid workload: gamma = 0.01 (alpha from the
+    # oracle's Laplace-law calibration), 45 deg, Ca = 1e-5 (Q* = Ca gamma eps A / mu_w)
+    mask, kw, info = bench.make_workload(bench.CONFIGS["pack384c"])
+    print(f"colour full: mask {mask.shape}, porosity {info['porosity']:.3f}", flush=True)
+    q = kw["q_target"]
+    lat = fluxlbm.Lattice(mask, watchdog_every=10, **kw)
     try:
         z = lat.coords()[:, 2]
         na = (z < 6).astype(float)

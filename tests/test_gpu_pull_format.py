@@ -1,7 +1,7 @@
 """The compact pull tables address the same slots as the int32 table, so a
 lattice stepped with any of them must hold bitwise equal states and
-histories: for every storage precision, BGK and MRT, with the default
-forms, with a mix of 8-bit, 16-bit and int32 tiles (small code limits, and
+histories: for every storage precision, BGK, MRT and the two-fluid colour
+model (both of its passes read the table), with the default forms, with a mix of 8-bit, 16-bit and int32 tiles (small code limits, and
 a lattice whose wide reservoir planes overflow the 16-bit codes at a
 y-wrap), and inside a batch that mixes the formats."""
 import numpy as np
@@ -88,3 +88,37 @@ def test_batch_mixing_formats_equals_singles():
         b.close()
         for l in singles + batched:
             l.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+@pytest.mark.parametrize("fmt,limits", [(2, (0, 0)), (2, (600, 100)), (1, (0, 0))])
+def test_colour_compact_equals_int32_bitwise(precision, fmt, limits):
+    """Colour model, flux set-up with a non-wetting inlet reservoir: the phase
+    pass (directions 1..6) and the colour step (all 18, and the neighbours'
+    phase through the same decoded indices) give bitwise equal f, A and B."""
+    mask = _pack(40, 12)
+    print(f"colour pull format: {precision} format {fmt} limits {limits}", flush=True)
+    sites = inputs.pore_sites(mask)
+    z = sites // (mask.shape[1] * mask.shape[2])
+    na = (z < 3).astype(float)
+
+    def run(f, lim):
+        lat = fluxlbm.Lattice(mask, precision=precision, model="colour", tau=1.0, q_target=0.05,
+                              alpha=0.01, beta=0.7, phi_solid=-0.7, watchdog_every=20)
+        try:
+            lat.set_pull_format(f, *lim)
+            info = lat.pull_format()
+            lat.init_colour(na, 1.0 - na)
+            lat.step(40)
+            A, B = lat.read_colour()
+            return lat.read_distributions(), A, B, lat.history(40), info
+        finally:
+            lat.close()
+
+    f0, A0, B0, h0, i0 = run(fluxlbm.FLBM_PULL_INT32, (0, 0))
+    f1, A1, B1, h1, i1 = run(fmt, limits)
+    assert i0[:3] == (fluxlbm.FLBM_PULL_INT32, 0, 0) and i1[0] == fmt
+    if limits != (0, 0):
+        assert i1[1] > 0 and i1[2] > 0 and i1[1] + i1[2] < i1[3]
+    assert np.array_equal(f0, f1) and np.array_equal(A0, A1) and np.array_equal(B0, B1)
+    assert np.array_equal(h0[:, :3], h1[:, :3])
