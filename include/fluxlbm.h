@@ -61,6 +61,7 @@ typedef int32_t flbm_status;
 #define FLBM_EINDEX (-6)    /* 19 * padded sites does not fit a signed 32-bit index */
 #define FLBM_EBOUND (-7)    /* caller's device buffer is smaller than flbm_device_bytes */
 #define FLBM_ESTATE (-8)    /* call not valid in the context's current state */
+#define FLBM_ESCRATCH (-9)  /* input larger than the allocation-free entry point's scratch holds */
 
 /* Storage precision of the distributions. Boundary sums and the inlet
  * density are FP64 in every mode. */
@@ -421,6 +422,34 @@ flbm_status flbm_debug_set_collision(flbm_ctx *c, int32_t enabled);
 /* Total mass, max |u| and a non-finite flag of the current state, computed
  * on the device from the stored distributions (synchronises). */
 flbm_status flbm_get_observables(flbm_ctx *c, double *mass, double *umax, int32_t *nonfinite);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * observables of flbm_get_observables -- total mass sum_s rho_s, max |u|
+ * (NaN if any value is not finite) and a non-finite flag -- of a state the
+ * caller holds on the device, without a context and without allocating.
+ *   f_dev      device distributions [19][n_pad] of the storage precision as
+ *              deviations f - w_q (the layout flbm_device_layout gives);
+ *              only read. Sites n_sites..n_pad-1 must hold zero deviations.
+ *   precision  FLBM_FP64 / FLBM_FP32 / FLBM_FP16DEV (scaled deviations)
+ *   n_sites    pore sites (mass counts rho - 1 over n_pad sites, plus n_sites)
+ *   n_pad      padded site count, a multiple of 256, at most 67,108,864
+ *              (FLBM_ESCRATCH beyond: the partial sums of its 256-site
+ *              blocks live in a fixed device array of the library, about
+ *              4 MiB per GPU, held until the process ends)
+ *   rho0       reference density (u = j / rho0)
+ *   hip_stream the work is enqueued there and the call synchronises it
+ *   mass, umax, nonfinite  host outputs, any may be NULL
+ * No device memory is allocated: the library's array is located once per
+ * device (on the first call with that device current). Every call on a GPU
+ * shares that GPU's array and rewrites the parts it reads, so calls that
+ * overlap on one GPU (other threads or streams) race and must be serialised
+ * by the caller. Errors: FLBM_EINVAL (null f_dev, n_sites outside [0,
+ * n_pad], n_pad not a positive multiple of 256, rho0 <= 0, unknown
+ * precision), FLBM_ESCRATCH, FLBM_EHIP. */
+flbm_status flbm_state_observables_noalloc(const void *f_dev, int32_t precision, int64_t n_sites, int64_t n_pad,
+                                           double rho0, void *hip_stream, double *mass, double *umax,
+                                           int32_t *nonfinite);
 
 /* Device pointers of the current distribution buffer (layout [19][n_pad] of
  * the storage type, deviations f - w_q) and of the pull table (int32

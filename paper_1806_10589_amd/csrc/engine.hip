@@ -1474,6 +1474,7 @@ const char *flbm_status_string(flbm_status s)
     case FLBM_EINDEX: return "lattice too large for 32-bit indices";
     case FLBM_EBOUND: return "device buffer too small";
     case FLBM_ESTATE: return "call not valid in the current state";
+    case FLBM_ESCRATCH: return "input larger than the allocation-free scratch holds (67,108,864 padded sites)";
     default: return "unknown status";
     }
 }
@@ -1905,5 +1906,105 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
 }
 
 const char *flbm_batch_last_error(const flbm_batch *b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ======================================================================
+// Observables of a caller-held state without allocating: the two kernels of
+// flbm_get_observables (per-block partials, then one block reducing them)
+// with their partials and result record in a file-scope device array.
+
+namespace {
+
+constexpr int NOALLOC_MAX_BLOCKS = 1 << 18;  // partial slots: 256-site blocks, 67,108,864 sites
+constexpr size_t NOALLOC_STATE_BYTES = (sizeof(DevState) + 255) / 256 * 256;
+constexpr size_t NOALLOC_BYTES =
+    NOALLOC_STATE_BYTES + (size_t)NOALLOC_MAX_BLOCKS * (sizeof(double) + sizeof(float) + sizeof(uint32_t));
+
+// One copy per device, held until the process ends. Host code never uses
+// this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The device address of `scratch` on the current device (looked up on the
+// first call there).
+hipError_t scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+flbm_status flbm_state_observables_noalloc(const void *f_dev, int32_t precision, int64_t n_sites, int64_t n_pad,
+                                           double rho0, void *hip_stream, double *mass, double *umax,
+                                           int32_t *nonfinite)
+{
+    if (!f_dev || n_sites < 0 || n_pad < 1 || n_sites > n_pad || n_pad % BLOCK != 0 || !(rho0 > 0.0) ||
+        (precision != FLBM_FP64 && precision != FLBM_FP32 && precision != FLBM_FP16DEV))
+        return FLBM_EINVAL;
+    const int64_t blocks = n_pad / BLOCK;
+    if (blocks > NOALLOC_MAX_BLOCKS) return FLBM_ESCRATCH;
+    void *base = nullptr;
+    if (scratch_address(&base) != hipSuccess) return FLBM_EHIP;
+    hipStream_t s = (hipStream_t)hip_stream;
+    char *sp = (char *)base;
+    DevState *st = (DevState *)sp;
+    double *pm = (double *)(sp + NOALLOC_STATE_BYTES);
+    float *pu = (float *)(pm + NOALLOC_MAX_BLOCKS);
+    uint32_t *pb = (uint32_t *)(pu + NOALLOC_MAX_BLOCKS);
+    // every call writes the partials of all its blocks and the result fields
+    // before reading them: nothing needs clearing
+    const dim3 grid((unsigned)blocks), block(BLOCK);
+    if (precision == FLBM_FP64)
+        hipLaunchKernelGGL(k_state_observables<double>, grid, block, 0, s, (const double *)f_dev, n_pad, 1.0 / rho0,
+                           pm, pu, pb);
+    else if (precision == FLBM_FP32)
+        hipLaunchKernelGGL(k_state_observables<float>, grid, block, 0, s, (const float *)f_dev, n_pad, 1.0 / rho0,
+                           pm, pu, pb);
+    else
+        hipLaunchKernelGGL(k_state_observables<_Float16>, grid, block, 0, s, (const _Float16 *)f_dev, n_pad,
+                           1.0 / rho0, pm, pu, pb);
+    ObsArgs a{};
+    a.n = n_sites;
+    a.tiles = (int32_t)blocks;
+    a.hist_cap = 1;
+    a.umax_limit = 0.0;
+    a.to_history = 0;
+    a.raise_flag = 0;
+    a.st = st;
+    a.obs_mass = pm;
+    a.obs_umax2 = pu;
+    a.obs_bad = pb;
+    hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return FLBM_EHIP;
+    double res[2];
+    uint32_t bad = 0;
+    if (hipMemcpyAsync(res, &st->obs_mass, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&bad, &st->obs_bad, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return FLBM_EHIP;
+    if (mass) *mass = res[0];
+    if (umax) *umax = res[1];
+    if (nonfinite) *nonfinite = (int32_t)bad;
+    return FLBM_OK;
+}
 
 }  // extern "C"

@@ -24,6 +24,7 @@ FLBM_EUNSTABLE = -5
 FLBM_EINDEX = -6
 FLBM_EBOUND = -7
 FLBM_ESTATE = -8
+FLBM_ESCRATCH = -9
 
 FLBM_FP64, FLBM_FP32, FLBM_FP16DEV = 0, 1, 2
 FLBM_BGK, FLBM_COLOUR, FLBM_MRT = 0, 1, 2
@@ -115,6 +116,8 @@ _SIGS = {
     "flbm_load_state": [_P, _P, ctypes.c_size_t],
     "flbm_debug_set_collision": [_P, _I32],
     "flbm_get_observables": [_P, _DP, _DP, ctypes.POINTER(_I32)],
+    "flbm_state_observables_noalloc": [_P, _I32, ctypes.c_int64, ctypes.c_int64, _D, _P, _DP, _DP,
+                                       ctypes.POINTER(_I32)],
     "flbm_device_layout": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), _I64P],
     "flbm_profile_kernels": [_P, _I32, _DP, _DP],
     "flbm_copy_kernel": [_P, _P, ctypes.c_size_t, _P],
@@ -376,6 +379,17 @@ def flbm_get_observables(ctx):
     m, u, b = _D(), _D(), _I32()
     _check(load_library().flbm_get_observables(ctx, ctypes.byref(m), ctypes.byref(u), ctypes.byref(b)),
            "flbm_get_observables", ctx)
+    return float(m.value), float(u.value), int(b.value)
+
+
+def flbm_state_observables_noalloc(f_dev: int, precision: int, n_sites: int, n_pad: int, rho0: float,
+                                   stream: int | None):
+    """(mass, max |u|, non-finite flag) of a device state [19][n_pad] the
+    caller holds, by the allocation-free entry point."""
+    m, u, b = _D(), _D(), _I32()
+    _check(load_library().flbm_state_observables_noalloc(f_dev, precision, n_sites, n_pad, rho0, stream,
+                                                         ctypes.byref(m), ctypes.byref(u), ctypes.byref(b)),
+           "flbm_state_observables_noalloc")
     return float(m.value), float(u.value), int(b.value)
 
 
