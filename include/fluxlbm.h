@@ -39,6 +39,14 @@
  *     launches every step directly instead of replaying captured graphs;
  *     FLBM_NO_BUF=1 takes the 64-bit addressing path of lattices past 4 GiB
  *     (no raw buffer instructions, no compact pull table) at any size.
+ *   - Profiling: FLBM_PROFILE=1 at flbm_create puts a roctx range (recorded
+ *     by rocprofv3 --marker-trace) around flbm_step, flbm_batch_step and
+ *     every kernel launch of a step -- "flbm phase pass", "flbm colour step",
+ *     "flbm stream-collide", "flbm step finalize", "flbm observables",
+ *     "flbm controller" -- and launches steps directly instead of replaying
+ *     graphs, so each kernel lies inside its range. The roctx library is
+ *     opened at run time; without it the ranges are no-ops. Results are
+ *     unchanged.
  */
 #ifndef FLUXLBM_H
 #define FLUXLBM_H
@@ -332,9 +340,12 @@ flbm_status flbm_batch_time(flbm_batch *b, int32_t n, double *ms_per_step);
  * unit, the three orders, 1 / 4 / 16 tiles per item) by timing trial_steps
  * launches of each, with both register budgets for one block per single-tile
  * item (1 + trial_steps steps of every sample per candidate: the samples
- * advance), or take it from cache_path (text lines "arch precision
- * log2(sites) grid order tiles_per_item occupancy ms"; NULL: no cache),
- * where a new choice is appended. The chosen schedule is set. */
+ * advance), or take it from cache_path (text lines "v2 arch precision model
+ * pull_formats log2(sites) grid order tiles_per_item occupancy ms", with
+ * pull_formats a bit mask of the pull-table formats the samples read: 1 the
+ * int32 table, 2 16-bit codes, 4 compact codes; lines without the "v2" tag
+ * are ignored; NULL: no cache), where a new choice is appended. The chosen
+ * schedule is set. */
 flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t trial_steps, flbm_schedule *best,
                                 double *best_ms);
 const char *flbm_batch_last_error(const flbm_batch *b);

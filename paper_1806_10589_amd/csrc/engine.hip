@@ -30,6 +30,7 @@
 #include "colour.h"
 #include "kernels.h"
 #include "lattice.h"
+#include "markers.h"
 #include "mlp.h"
 #include "mlp_ctx.h"
 
@@ -101,6 +102,7 @@ struct flbm_ctx {
     int chunk = 0;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     bool use_graph = true;
+    bool markers = false;  // FLBM_PROFILE=1: roctx ranges per launch, direct launches (no graphs)
 };
 
 namespace {
@@ -330,10 +332,13 @@ void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
     p.phi = c->phi;
     StepArgs a = step_args(c);
     a.rd = from;
-    if (c->use_buf)
-        hipLaunchKernelGGL(k_phase_buf<T>, dim3(c->tiles), dim3(TILE / PHASE_V), 0, s, p, a);
-    else
-        hipLaunchKernelGGL(k_phase<T>, dim3(c->blocks256), dim3(BLOCK), 0, s, p);
+    {
+        Range r(c->markers, "flbm phase pass");
+        if (c->use_buf)
+            hipLaunchKernelGGL(k_phase_buf<T>, dim3(c->tiles), dim3(TILE / PHASE_V), 0, s, p, a);
+        else
+            hipLaunchKernelGGL(k_phase<T>, dim3(c->blocks256), dim3(BLOCK), 0, s, p);
+    }
     ColourStepArgs cs{};
     cs.alpha = c->p.alpha;
     cs.beta = c->p.beta;
@@ -344,6 +349,7 @@ void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
     cs.about = c->cab[from ^ 1];
     const T *fin = (const T *)c->f[from];
     T *fout = (T *)c->f[from ^ 1];
+    Range r(c->markers, "flbm colour step");
     if (c->use_buf) {
         const dim3 grid(c->tiles);
         if (obs)
@@ -363,6 +369,7 @@ void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
 template <typename T, bool MRT>
 void launch_stream_collide_c(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bool obs, const StepArgs &a)
 {
+    Range r(c->markers, "flbm stream-collide");
     const dim3 grid(c->tiles), block(SC_BLOCK);
     if (c->use_buf) {
         if (obs)
@@ -392,6 +399,7 @@ void launch_stream_collide(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bo
 // Q_out, the next inlet sum, the history record and the step counter.
 void launch_finalize(flbm_ctx *c, hipStream_t s, int from)
 {
+    Range r(c->markers, "flbm step finalize");
     StepArgs a = step_args(c);
     a.rd = from;
     hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(FIN_BLOCK), 0, s, a);
@@ -405,7 +413,10 @@ void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
     T *fout = (T *)c->f[from ^ 1];
     launch_stream_collide<T>(c, s, fin, fout, obs);
     launch_finalize(c, s, from);
-    if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
+    if (obs) {
+        Range r(c->markers, "flbm observables");
+        hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
+    }
 }
 
 void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
@@ -413,7 +424,10 @@ void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
     if (c->colour) {
         with_storage(c, [&](auto tag) { launch_colour_step<decltype(tag)>(c, s, from, obs); });
         launch_finalize(c, s, from);
-        if (obs) hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
+        if (obs) {
+            Range r(c->markers, "flbm observables");
+            hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
+        }
         return;
     }
     with_storage(c, [&](auto tag) { launch_step<decltype(tag)>(c, s, from, obs); });
@@ -563,7 +577,10 @@ void launch_controller(flbm_ctx *c, hipStream_t s, int rd_next)
 void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
 {
     launch_step_plain(c, s, from, obs);
-    if (c->ctrl_on) launch_controller(c, s, from ^ 1);
+    if (c->ctrl_on) {
+        Range r(c->markers, "flbm controller");
+        launch_controller(c, s, from ^ 1);
+    }
 }
 
 void drop_graphs(flbm_ctx *c)
@@ -793,6 +810,11 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
     c->chunk = std::max(2, w + (w & 1));
     const char *ng = std::getenv("FLBM_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
+    // FLBM_PROFILE=1: a roctx range around every kernel launch of a step,
+    // which therefore launches directly instead of replaying graphs
+    const char *pf = std::getenv("FLBM_PROFILE");
+    c->markers = pf && pf[0] == '1';
+    if (c->markers) c->use_graph = false;
     c->dbytes = carve(c, nullptr);
     // No usable device is not an error yet: the host-side lattice queries
     // work without one, and the first device call reports the HIP error.
@@ -1220,6 +1242,7 @@ flbm_status flbm_debug_set_collision(flbm_ctx *c, int32_t enabled)
 flbm_status flbm_step(flbm_ctx *c, int32_t n)
 {
     if (!c || n < 0) return FLBM_EINVAL;
+    Range r(c->markers, "flbm_step");
     flbm_status rc = ensure_device(c);
     if (rc) return rc;
     if (n > 0) {
@@ -1763,6 +1786,7 @@ flbm_status flbm_batch_step(flbm_batch *b, int32_t n)
 {
     if (!b || n < 0) return FLBM_EINVAL;
     if (n == 0) return FLBM_OK;
+    Range r(!b->s.empty() && b->s[0]->markers, "flbm_batch_step");
     BHIPCHK(b, hipSetDevice(b->device));
     flbm_status rc = batch_refresh(b);
     if (rc) return rc;
@@ -1843,17 +1867,31 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
     int bucket = 0;
     while ((int64_t{1} << (bucket + 1)) <= sites) ++bucket;
     const int prec = b->precision;
-    const std::string key = arch + " " + std::to_string(prec) + " " + std::to_string(bucket);
+    // the collision model and the pull-table formats in use change the
+    // kernels, so they are part of the key: bit 0 int32 table, bit 1 16-bit
+    // codes, bit 2 compact (8- and 16-bit) codes
+    const int model = b->s.empty() ? 0 : b->s[0]->p.model;
+    int formats = 0;
+    for (flbm_ctx *c : b->s) {
+        const bool coded = c->use_buf && c->pull.tiles > 0 && c->pull_format != FLBM_PULL_INT32;
+        formats |= coded ? (c->pull_format == FLBM_PULL_HALF ? 2 : 4) : 1;
+    }
     const int chunk = b->sched.chunk;
-    // a cached choice for this architecture, precision and size bucket
+    // a cached choice for this architecture, precision, model, formats and
+    // size bucket; lines of other layouts (no "v2" tag) never match
     if (cache_path) {
         FILE *fp = std::fopen(cache_path, "r");
         if (fp) {
-            char a[64];
-            int p, bk, g, o, t, occ;
-            double ms;
-            while (std::fscanf(fp, "%63s %d %d %d %d %d %d %lf", a, &p, &bk, &g, &o, &t, &occ, &ms) == 8) {
-                if (arch == a && p == prec && bk == bucket) {
+            char line[256];
+            while (std::fgets(line, sizeof(line), fp)) {
+                char tag[8], a[64];
+                int p, m, fm, bk, g, o, t, occ;
+                double ms;
+                if (std::sscanf(line, "%7s %63s %d %d %d %d %d %d %d %d %lf", tag, a, &p, &m, &fm, &bk, &g, &o, &t,
+                                &occ, &ms) != 11 ||
+                    std::strcmp(tag, "v2") != 0)
+                    continue;
+                if (arch == a && p == prec && m == model && fm == formats && bk == bucket) {
                     std::fclose(fp);
                     flbm_schedule s{g, o, t, chunk, occ};
                     flbm_status rc = flbm_batch_set_schedule(b, &s);
@@ -1895,8 +1933,8 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
     if (cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
         if (fp) {
-            std::fprintf(fp, "%s %d %d %d %d %d %d %.6f\n", arch.c_str(), prec, bucket, bs.grid, bs.order,
-                         bs.tiles_per_item, bs.occupancy, bms);
+            std::fprintf(fp, "v2 %s %d %d %d %d %d %d %d %d %.6f\n", arch.c_str(), prec, model, formats, bucket,
+                         bs.grid, bs.order, bs.tiles_per_item, bs.occupancy, bms);
             std::fclose(fp);
         }
     }

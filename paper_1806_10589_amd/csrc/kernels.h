@@ -166,6 +166,11 @@ struct PlaneArgs {
 // differ between directions by a fixed amount at every site -- a Weyl step
 // -- bias the steady flux by 1 % on a test pack; independent ones leave
 // 0.1-0.2 %.) They depend on nothing else, so runs stay deterministic.
+// The site hash is the published 32-bit integer mix known as "lowbias32"
+// (xorshift-multiply rounds with the multipliers 0x7feb352d and 0x846ca68b,
+// from C. Wellons' hash-prospector search); the per-direction constants are
+// the golden-ratio increment 0x9e3779b9 and the MurmurHash3 finalizer
+// multiplier 0x85ebca6b.
 __device__ __forceinline__ uint32_t dither_hash(uint32_t x)
 {
     x ^= x >> 16;

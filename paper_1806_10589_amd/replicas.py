@@ -144,6 +144,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("case", choices=["e1", "e2", "laplace"])
     ap.add_argument("--gamma", type=float, default=6e-5)
+    ap.add_argument("--reservoir", type=int, default=6,
+                    help="pure-fluid planes at each end of the drainage tube (e2)")
     a = ap.parse_args(argv)
     if a.case == "e1":
         for u in (1e-3, 5e-3, 1e-2):
@@ -155,7 +157,7 @@ def main(argv=None):
         alpha = a.gamma * 0.005 / slope
         print(json.dumps(dict(gamma_per_alpha=slope / 0.005, alpha=alpha)), flush=True)
         for q in (2.0, 0.2, 0.02):
-            print(json.dumps(e2_drainage(q, alpha)), flush=True)
+            print(json.dumps(e2_drainage(q, alpha, reservoir=a.reservoir)), flush=True)
 
 
 if __name__ == "__main__":

@@ -310,3 +310,17 @@ def test_no_buffer_path_has_no_compact_pull_table(monkeypatch):
             assert e.value.status == fluxlbm.FLBM_ESTATE
     finally:
         fluxlbm.flbm_destroy(ctx)
+
+
+def test_profiling_switch_on_the_host(monkeypatch):
+    """FLBM_PROFILE=1 opens the roctx library lazily; on a host without a GPU
+    a step still fails cleanly with a HIP error and no crash."""
+    mask = inputs.random_mask((6, 8, 8), 0.2, 5)
+    mask[0] = 0
+    monkeypatch.setenv("FLBM_PROFILE", "1")
+    ctx = fluxlbm.flbm_create(mask, _params(mask))
+    try:
+        rc = fluxlbm.load_library().flbm_step(ctx, 3)
+        assert rc in (fluxlbm.FLBM_OK, fluxlbm.FLBM_EHIP)
+    finally:
+        fluxlbm.flbm_destroy(ctx)

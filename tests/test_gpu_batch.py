@@ -141,6 +141,15 @@ def test_autotune_picks_and_caches_a_schedule(tmp_path):
     s2, ms2 = b.autotune(cache, trial_steps=2)
     assert s2 == s1 and ms2 == pytest.approx(ms1, rel=1e-4, abs=1e-6)  # cached to 1 ns
     assert len([l for l in open(cache).read().split("\n") if l.strip()]) == 1
+    # the key holds the model and the pull-table formats: with the int32
+    # table the cached compact-table choice is not reused, a new one is added
+    tag, _, prec, model, formats = open(cache).read().split()[:5]
+    assert tag == "v2" and prec == "1" and model == "0" and formats == "4"
+    for _, l in batched:
+        l.set_pull_format(fluxlbm.FLBM_PULL_INT32)
+    b.autotune(cache, trial_steps=2)
+    lines = [l.split() for l in open(cache).read().split("\n") if l.strip()]
+    assert len(lines) == 2 and lines[1][4] == "1"
     # the tuned batch still steps correctly: compare with singles from here
     singles = [fluxlbm.Lattice(m, precision="fp32", tau=t[3], q_target=t[4], rho_out=t[5])
                for (m, _), t in zip(batched, SPECS)]

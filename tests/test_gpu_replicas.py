@@ -4,8 +4,12 @@ six-layer reservoirs, interfacial tension 6e-5 set through alpha from a
 Laplace-law calibration of the same code. The paper's observation: the rate
 at which the wetting volume falls approaches the injected flux Q once the
 displacement is steady (the early deviation is the capillary entry effect).
-The run with Q = 0.02 needs 4e5 steps and is left to
-``python -m paper_1806_10589_amd.replicas e2``."""
+At the lowest flux, Q = 0.02, the paper notes that spurious currents near
+the boundaries can spoil this and that larger reservoirs mitigate it: with
+six-plane reservoirs the rate is still 19 % above Q after 2.56M steps (1.45
+falling to 1.19), with twelve-plane reservoirs it stays within 2-4 % of Q
+from the start (0.98 to 0.96 over the same run); the test takes the
+twelve-plane set-up."""
 import numpy as np
 import pytest
 
@@ -36,3 +40,12 @@ def test_drainage_rate_approaches_flux_q02(alpha):
     assert abs(track[-1] - 1.0) <= 0.04, track
     # and the deviation keeps shrinking
     assert abs(track[-1] - 1.0) < abs(track[len(track) // 4] - 1.0)
+
+
+def test_drainage_rate_near_flux_q002_with_larger_reservoirs(alpha):
+    r = replicas.e2_drainage(0.02, alpha, reservoir=12, steps=640000, window=128000)
+    track = np.array(r["rate_track"])
+    print(f"Q = 0.02, 12-plane reservoirs: rate/Q {r['rate_over_q']:.4f}, track {np.round(track, 3)}", flush=True)
+    assert r["q_in_err"] <= 1e-12
+    assert abs(r["rate_over_q"] - 1.0) <= 0.05, track
+    assert abs(track[len(track) // 2:] - 1.0).max() <= 0.05, track
