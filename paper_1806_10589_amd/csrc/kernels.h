@@ -732,6 +732,19 @@ __device__ __forceinline__ void rescale_pops(R (&g)[19])
     }
 }
 
+// The byte codes of V consecutive sites from s0 (see pull_format.h):
+// directions 1..16 in four words per site (w[k] holds 4k+1..4k+4), 17 and
+// 18 in a 16-bit tail.
+template <int V>
+__device__ __forceinline__ void load_byte_codes(__amdgpu_buffer_rsrc_t rb, uint32_t s0, uint32_t npad,
+                                                uint32_t (&w)[4][V], uint16_t (&tl)[V])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        buf_load_v<V, uint32_t, uint32_t, SC_IDX_AUX>(rb, s0 * 4u, (uint32_t)k * npad * 4u, w[k]);
+    buf_load_v<V, uint16_t, uint16_t, SC_IDX_AUX>(rb, s0 * 2u, 16u * npad, tl);
+}
+
 // The work of one tile (SC_BLOCK threads), shared by the single-lattice
 // kernel (one tile per block) and the batched kernel (a work list of tiles
 // of many lattices per block).
@@ -761,20 +774,26 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
             for (int v = 0; v < V; ++v) g[v][0] = load_pop<T, SCALED>(r[v], 0);
         }
         const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
+        // FP16 loads the byte codes before the tile's form is known, so that
+        // their latency overlaps the header's (wasted on the few tiles of
+        // another form, whose byte rows are zero): 6 % off the FP16 step,
+        // which waits on latency, and 1 % onto the FP32 step and the colour
+        // passes, which wait on bandwidth
+        constexpr bool SPEC = std::is_same<T, _Float16>::value;
+        uint32_t w[4][V];
+        uint16_t tl[V];
+        if constexpr (SPEC) {
+            if (hdr) load_byte_codes<V>(make_rsrc(a.pull_bytes, a.bytes_bytes), (uint32_t)s0, (uint32_t)npad, w, tl);
+        }
         const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
         const uint32_t sent = 19u * (uint32_t)npad;
         // position of each of this thread's sites in the tile
         const uint32_t p0 = (uint32_t)(s0 - (int64_t)tile * TILE);
         if (form == PULL_TILE_BYTE) {
-            // byte codes: four words for directions 1..16, a 16-bit row for
-            // 17 and 18; flat index = base + position + code
-            const __amdgpu_buffer_rsrc_t rb = make_rsrc(a.pull_bytes, a.bytes_bytes);
-            uint32_t w[4][V];
-            uint16_t tl[V];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                buf_load_v<V, uint32_t, uint32_t, SC_IDX_AUX>(rb, vi, (uint32_t)k * (uint32_t)npad * 4u, w[k]);
-            buf_load_v<V, uint16_t, uint16_t, SC_IDX_AUX>(rb, (uint32_t)s0 * 2u, 16u * (uint32_t)npad, tl);
+            // byte codes: directions 1..16 in four words, 17 and 18 in a
+            // 16-bit tail; flat index = base + position + code
+            if constexpr (!SPEC)
+                load_byte_codes<V>(make_rsrc(a.pull_bytes, a.bytes_bytes), (uint32_t)s0, (uint32_t)npad, w, tl);
 #pragma unroll
             for (int q = 1; q < 19; ++q) {
                 const uint32_t base = (uint32_t)hdr[q - 1];
