@@ -293,20 +293,28 @@ def run_batch(args, cfg):
     print(json.dumps(out), flush=True)
 
 
-def controller_ab(max_steps=300000):
+def controller_ab(n=128, margin_frac=0.25, max_steps=None):
     """Steps to |Q_out - Q*| / Q* <= 1e-3 (two-step mean, for good), plain
-    update versus the trained controller, on a held-out 128^3 pack
-    (porosity 0.25, seed 5001, tau 0.8, Darcy velocity 1e-5), same GPU."""
+    update versus the trained controller, on a held-out n^3 pack (porosity
+    0.25, seed 5001, tau 0.8, Darcy velocity 1e-5), same GPU; the run goes
+    on for margin_frac of the settling time after it. The 512^3 comparison
+    takes about 20 minutes (two runs of some 500,000 steps)."""
     from paper_1806_10589_amd import controller
 
     if not os.path.exists(controller.DEFAULT_WEIGHTS):
         return None
     params, meta = controller.load_weights()
-    mask, kw = controller.make_sample(128, 0.25, 5001, tau=0.8, darcy=1e-5)
-    r = controller.evaluate(params, mask, kw, max_steps=max_steps, settings=controller.settings_of(meta))
-    return {"workload": "pack128 held out (phi 0.25, seed 5001, tau 0.8, darcy 1e-5), FP32",
-            "tol": 1e-3, "plain_steps": r["plain_steps"], "learned_steps": r["learned_steps"],
-            "gain": r.get("gain"), "controller": list(r["controller"]) if r.get("controller") else None}
+    mask, kw = controller.make_sample(n, 0.25, 5001, tau=0.8, darcy=1e-5)
+    if max_steps is None:
+        max_steps = max(300000, 4 * n * n)
+    progress = (lambda m: print(m, file=sys.stderr, flush=True)) if n > 128 else None
+    r = controller.evaluate(params, mask, kw, max_steps=max_steps, settings=controller.settings_of(meta),
+                            margin_frac=margin_frac, progress=progress)
+    return {"workload": f"pack{n} held out (phi 0.25, seed 5001, tau 0.8, darcy 1e-5), FP32",
+            "tol": 1e-3, "margin_frac": margin_frac, "plain_steps": r["plain_steps"],
+            "learned_steps": r["learned_steps"], "gain": r.get("gain"),
+            "plain_secs": round(r["plain_secs"], 1), "learned_secs": round(r["learned_secs"], 1),
+            "controller": list(r["controller"]) if r.get("controller") else None}
 
 
 def copy_bandwidth(torch, nbytes=2 << 30, reps=20):
@@ -479,6 +487,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-controller", action="store_true")
+    ap.add_argument("--controller-n", type=int, default=128,
+                    help="edge of the held-out pack of the learned-versus-plain comparison "
+                         "(512: the 35.5M-site pack, about 20 minutes)")
+    ap.add_argument("--controller-margin-frac", type=float, default=0.25,
+                    help="steps run on after settling, as a fraction of the settling time "
+                         "(the committed 512^3 comparison used 0.1)")
     ap.add_argument("--pull", choices=["compact", "half", "int32"], default="compact",
                     help="pull-table format of the step: 8/16-bit codes, 16-bit codes, or the int32 table")
     args = ap.parse_args()
@@ -570,7 +584,7 @@ def main():
     if args.config == "pack256" and not args.no_pack512:
         out["pack512"] = pack512_line(args)
     if not args.no_controller and args.config == "pack256":
-        out["controller_ab"] = controller_ab()
+        out["controller_ab"] = controller_ab(args.controller_n, args.controller_margin_frac)
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         out["cpu_baseline"] = cpu_baseline(mask, kw, args.cpu_steps, steps_t1=args.cpu_steps_1_thread)
     print(json.dumps(out), flush=True)
