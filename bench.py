@@ -76,12 +76,17 @@ CONFIGS = {
 SCHEDULE_CACHE = os.path.join(ROOT, "paper_1806_10589_amd", "schedule_cache.txt")
 
 
-def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share16: float = 0.0) -> float:
+def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share16: float = 0.0,
+                  share_run: float = 0.0, share_wide: float = 0.0) -> float:
     """Algorithmic bytes of one pore-site update in this design: 19
     populations read and written once in the storage type, plus the pull
     table: 18 int32 indices, or, on the shares of tiles that read compact
     codes, 18 8-bit or 16-bit codes and the tile's 80-byte header over its
-    512 sites. The colour model adds, per site: in the phase pass the 7
+    512 sites; of the 8-bit tiles, the share share_run that the step reads as
+    run codes takes 8 bytes per site instead of 18, and 4 more on the share
+    share_wide of waves (of all waves) whose list of codes needs a second
+    word (not in FP16 storage, whose steps read the 8-bit codes).
+    The colour model adds, per site: in the phase pass the 7
     colour pairs (A_q, B_q) read (6 of them pulled, with the codes of
     directions 1-6: 2 words of byte codes, 3 of 16-bit codes or 6 int32) and
     N_A + N_B and phi written; in the colour step phi (the neighbours' values
@@ -89,7 +94,10 @@ def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share
     colours are FP64 in FP64 storage and FP32 otherwise."""
     elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
     hdr = 80 / 512
-    table = 18 * 4 * (1.0 - share8 - share16) + (18 + hdr) * share8 + (36 + hdr) * share16
+    if precision == "fp16dev":
+        share_run = share_wide = 0.0
+    table = (18 * 4 * (1.0 - share8 - share16) + (18 + hdr) * (share8 - share_run) + (8 + hdr) * share_run
+             + 4 * share_wide + (36 + hdr) * share16)
     single = 19 * 2 * elem + table
     if model != "colour":
         return single
@@ -107,14 +115,19 @@ def bytes_per_lup_survey(precision: str, model: str = "bgk") -> float:
     return single if model != "colour" else single + 14 * 2 * elem + 4
 
 
+PULL_FORMATS = ("run", "compact", "half", "int32")
+
+
 def pull_share(lats, fmt: str):
     """Set the pull-table format of the lattices; return the shares of their
-    tiles that read 8-bit and 16-bit codes."""
+    tiles that read 8-bit and 16-bit codes, of the tiles whose 8-bit codes
+    the single-fluid step reads as run codes, and of the waves (64 sites)
+    whose run codes need a second word."""
     from paper_1806_10589_amd import fluxlbm
 
-    code = {"compact": fluxlbm.FLBM_PULL_COMPACT, "half": fluxlbm.FLBM_PULL_HALF,
+    code = {"run": fluxlbm.FLBM_PULL_RUN, "compact": fluxlbm.FLBM_PULL_COMPACT, "half": fluxlbm.FLBM_PULL_HALF,
             "int32": fluxlbm.FLBM_PULL_INT32}[fmt]
-    t8 = t16 = tiles = 0
+    t8 = t16 = tr = ww = tiles = 0
     for lat in lats:
         if lat.pull_format()[0] != code:
             lat.set_pull_format(code)
@@ -122,7 +135,11 @@ def pull_share(lats, fmt: str):
         t8 += a
         t16 += b
         tiles += t
-    return (t8 / tiles, t16 / tiles) if tiles else (0.0, 0.0)
+        if fmt == "run":
+            r, w = lat.pull_runs()
+            tr += r
+            ww += w
+    return (t8 / tiles, t16 / tiles, tr / tiles, ww / (8 * tiles)) if tiles else (0.0, 0.0, 0.0, 0.0)
 
 
 def kernel_source_hash(colour: bool = False) -> str:
@@ -264,7 +281,8 @@ def run_batch(args, cfg):
             "precision": cfg["precision"],
             "schedule": sched,
             "pull_table": args.pull,
-            "tile_share_8bit_16bit": [round(v, 4) for v in share],
+            "tile_share_8bit_16bit": [round(v, 4) for v in share[:2]],
+            "run_share_tiles_waves_wide": [round(v, 4) for v in share[2:]],
         },
         "status": "ok" if rc == fluxlbm.FLBM_OK else f"unstable (sample {bad})",
         "sequential_ms_per_step": round(ms_seq, 5),
@@ -493,8 +511,9 @@ def main():
     ap.add_argument("--controller-margin-frac", type=float, default=0.25,
                     help="steps run on after settling, as a fraction of the settling time "
                          "(the committed 512^3 comparison used 0.1)")
-    ap.add_argument("--pull", choices=["compact", "half", "int32"], default="compact",
-                    help="pull-table format of the step: 8/16-bit codes, 16-bit codes, or the int32 table")
+    ap.add_argument("--pull", choices=list(PULL_FORMATS), default="run",
+                    help="pull-table format of the step: 8/16-bit codes with run codes, 8/16-bit codes, "
+                         "16-bit codes, or the int32 table")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -569,7 +588,8 @@ def main():
             "precision": kw["precision"],
             "collision": kw.get("model", "bgk"),
             "pull_table": args.pull,
-            "tile_share_8bit_16bit": [round(v, 4) for v in share],
+            "tile_share_8bit_16bit": [round(v, 4) for v in share[:2]],
+            "run_share_tiles_waves_wide": [round(v, 4) for v in share[2:]],
             **info,
         },
         "hbm_gbs_model": round(mlups * roofline["bytes_per_lup"] / 1e3, 1),

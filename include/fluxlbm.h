@@ -318,7 +318,8 @@ typedef struct flbm_schedule {
     int32_t chunk;          /* steps per captured graph (>= 1; graphs are used when even) */
     int32_t occupancy;      /* 0: the compiler's register budget; 8: at most 64 VGPRs (8 waves per
                                SIMD) for the steps that record no observables; only for grid 0
-                               with one tile per item */
+                               with one tile per item, and only where that kernel needs no
+                               scratch (else the compiler's budget is used) */
 } flbm_schedule;
 
 /* samples: n context pointers (not copied beyond the call's lifetime of the
@@ -343,7 +344,7 @@ flbm_status flbm_batch_time(flbm_batch *b, int32_t n, double *ms_per_step);
  * advance), or take it from cache_path (text lines "v2 arch precision model
  * pull_formats log2(sites) grid order tiles_per_item occupancy ms", with
  * pull_formats a bit mask of the pull-table formats the samples read: 1 the
- * int32 table, 2 16-bit codes, 4 compact codes; lines without the "v2" tag
+ * int32 table, 2 16-bit codes, 4 compact codes, 8 run codes; lines without the "v2" tag
  * are ignored; NULL: no cache), where a new choice is appended. The chosen
  * schedule is set. */
 flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t trial_steps, flbm_schedule *best,
@@ -384,11 +385,21 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
  *                      code c <= 0xFFFD is the flat index base + c, 0xFFFE
  *                      the boundary-unknown sentinel, 0xFFFF the bounce-back
  *                      slot opp(q)*n_pad + site: 36 bytes per site.
- *   FLBM_PULL_COMPACT  (the default where available) as HALF, but a tile
- *                      whose sources fit takes 8-bit codes against the
- *                      site's position p in the tile: c <= 0xFD is base +
- *                      p + c, 0xFE the sentinel, 0xFF bounce-back: 18 bytes
- *                      per site.
+ *   FLBM_PULL_COMPACT  as HALF, but a tile whose sources fit takes 8-bit
+ *                      codes against the site's position p in the tile:
+ *                      c <= 0xFD is base + p + c, 0xFE the sentinel, 0xFF
+ *                      bounce-back: 18 bytes per site.
+ *   FLBM_PULL_RUN      (the default where available) as COMPACT, but the
+ *                      step (the colour model's second pass) reads the
+ *                      8-bit codes of a tile as run codes where it has
+ *                      them: per wave of 64 sites, a per-site mask of the
+ *                      directions whose code differs from the previous
+ *                      site's and the wave's list of those codes (at most
+ *                      512): 8 bytes per site, 12 where a wave lists more
+ *                      than 256 codes. Not in FP16 storage, whose steps
+ *                      read the 8-bit codes (decoding runs costs them more
+ *                      than the bytes saved). COMPACT and RUN share one
+ *                      table, so switching between them rebuilds nothing.
  * A tile whose sources of some direction span more than a form's range
  * falls back to the next wider form, down to the int32 table. Both passes of
  * the colour model read it too (the phase pass directions 1..6). Lattices
@@ -400,6 +411,7 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
 #define FLBM_PULL_INT32 0
 #define FLBM_PULL_HALF 1
 #define FLBM_PULL_COMPACT 2
+#define FLBM_PULL_RUN 3
 flbm_status flbm_set_pull_format(flbm_ctx *c, int32_t format, int32_t limit16, int32_t limit8);
 /* The format in use and, of the `tiles` tiles, how many read 8-bit and
  * 16-bit codes (the rest read the int32 table; both 0 for FLBM_PULL_INT32).
@@ -411,11 +423,26 @@ flbm_status flbm_pull_format_info(const flbm_ctx *c, int32_t *format, int64_t *t
  * [4][n_pad] (byte j of word k: direction 4k+j+1) and uint16 [n_pad]
  * (directions 17 in bits 0-7, 18 in bits 8-15), and the header int32
  * [tiles][20] (entries 0..17: the base of direction q at q-1; entry 18 the
- * tile's form: 0 int32 table, 1 16-bit, 2 8-bit; entry 19: 0). A tile's
- * rows in the forms it does not use are zero. Any pointer may be NULL.
- * Host-only; FLBM_ESTATE without a compact table. */
+ * tile's form: 0 int32 table, 1 16-bit, 2 8-bit; entry 19: 1 if the 8-bit
+ * tile also has run codes, else 0). A tile's rows in the forms it does not
+ * use are zero. Any pointer may be NULL. Host-only; FLBM_ESTATE without a
+ * compact table. */
 flbm_status flbm_get_compact_pull(const flbm_ctx *c, uint32_t *codes16, uint32_t *codes8, uint16_t *codes8_tail,
                                   int32_t *hdr);
+/* Of the 8-bit tiles, how many have run codes, and how many of their waves
+ * list more than 256 codes (12 bytes per site instead of 8). Host-only. */
+flbm_status flbm_pull_run_info(const flbm_ctx *c, int64_t *tiles_run, int64_t *waves_wide);
+/* Host copy of the run codes: uint32 [n_pad][2] (word 0: bit q-1 set where
+ * direction q's 8-bit code differs from the previous site's, always at a
+ * wave's first site (sites 64w); bit 31 set on every site of a wave whose
+ * list is longer than 256 bytes; word 1 of site 64w + l: bytes 4l..4l+3 of
+ * the wave's list, the listed codes direction by direction in site order)
+ * and uint32 [n_pad] (site 64w + l: bytes 256+4l..256+4l+3). Site 64w + l's
+ * code of direction q is list entry off + r, off the listed codes of the
+ * directions before q and r the listed codes of q at sites 64w..64w+l,
+ * minus one. Zero in tiles without run codes. Any pointer may be NULL.
+ * Host-only; FLBM_ESTATE without a compact table. */
+flbm_status flbm_get_pull_runs(const flbm_ctx *c, uint32_t *runs, uint32_t *runs_hi);
 
 /* Raw checkpoint of the stored state: flbm_state_bytes gives the size; save
  * copies the current distribution buffers (storage precision: f as

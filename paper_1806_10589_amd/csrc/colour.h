@@ -30,6 +30,53 @@ template <> struct ColourStore<_Float16> { using type = float; };
 // A pair of colour values (A then B; N_A then N_B) as one vector access.
 template <typename C> struct Pair { typedef C type __attribute__((ext_vector_type(2))); };
 
+// Stores of a colour pair (A, B) never exceed 8 bytes per lane: on gfx950 a
+// 16-byte vector store whose data registers the very next instruction
+// overwrites has stored the overwriting value in some lanes (the last four
+// of each group of sixteen), and the compiler emitted exactly that order for
+// FP64 pairs. Such a pair is stored as its two halves, with a compiler
+// barrier between them so that they are not merged back; FP32 pairs (8
+// bytes) stay one store.
+template <typename C>
+__device__ __forceinline__ void store_pair(typename Pair<C>::type *dst, C a, C b, bool nt)
+{
+    if constexpr (sizeof(C) <= 4) {
+        if (nt)
+            __builtin_nontemporal_store(typename Pair<C>::type{a, b}, dst);
+        else
+            *dst = typename Pair<C>::type{a, b};
+    } else {
+        C *d = (C *)dst;
+        if (nt)
+            __builtin_nontemporal_store(a, d);
+        else
+            d[0] = a;
+        __asm__ __volatile__("" ::: "memory");
+        if (nt)
+            __builtin_nontemporal_store(b, d + 1);
+        else
+            d[1] = b;
+    }
+}
+
+// The same through a buffer descriptor (non-temporal), pair element i of
+// the array the descriptor covers, row offset soff in bytes.
+template <typename C>
+__device__ __forceinline__ void buf_store_pair_nt(__amdgpu_buffer_rsrc_t r, uint32_t i, uint32_t soff, C a, C b)
+{
+    typedef typename RawBits<sizeof(C)>::type CB;
+    if constexpr (sizeof(C) <= 4) {
+        typedef typename RawBits<2 * sizeof(C)>::type CB2;
+        buf_store_raw_nt<2 * sizeof(C)>(__builtin_bit_cast(CB2, typename Pair<C>::type{a, b}), r,
+                                        i * 2u * (uint32_t)sizeof(C), soff);
+    } else {
+        buf_store_raw_nt<sizeof(C)>(__builtin_bit_cast(CB, a), r, i * 2u * (uint32_t)sizeof(C), soff);
+        __asm__ __volatile__("" ::: "memory");
+        buf_store_raw_nt<sizeof(C)>(__builtin_bit_cast(CB, b), r, i * 2u * (uint32_t)sizeof(C) + (uint32_t)sizeof(C),
+                                    soff);
+    }
+}
+
 // phi of the neighbour that pull direction p reads from, decoded from the
 // pull index: a regular pull q*n_pad + src gives phi[src]; bounce-back (a
 // solid or a non-periodic side) gives the wetting value phi_solid; a source
@@ -119,12 +166,12 @@ __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
     const R tot = na + nb;
     // non-temporal: the colour step reads these once per site (phi also from
     // the neighbours), after the whole pass has been written
-    __builtin_nontemporal_store(C2{(C)na, (C)nb}, &((C2 *)p.nab)[s]);
+    store_pair<C>(&((C2 *)p.nab)[s], (C)na, (C)nb, true);
     __builtin_nontemporal_store((C)(tot != (R)0 ? (na - nb) / tot : (R)0), &((C *)p.phi)[s]);
     if (p.st->omega == 0.0) {
         // testing aid (collision off): keep the streamed colours
 #pragma unroll
-        for (int q = 0; q < 7; ++q) ((C2 *)p.about)[(int64_t)q * npad + s] = C2{(C)a[q], (C)b[q]};
+        for (int q = 0; q < 7; ++q) store_pair<C>(&((C2 *)p.about)[(int64_t)q * npad + s], (C)a[q], (C)b[q], false);
     }
 }
 
@@ -233,8 +280,8 @@ __global__ __launch_bounds__(TILE, (sizeof(T) <= 4 && !OBS) ? 6 : 1) void k_colo
             }
             const R w = (R)d3q19::weight7(q);
             const R adv = (R)1 + (R)4.5 * cu;
-            __builtin_nontemporal_store(C2{(C)(w * (na * adv + bab * cn)), (C)(w * (nb * adv - bab * cn))},
-                                        &about[(int64_t)q * npad + s]);
+            store_pair<C>(&about[(int64_t)q * npad + s], (C)(w * (na * adv + bab * cn)), (C)(w * (nb * adv - bab * cn)),
+                          true);
         }
     }
 
@@ -562,15 +609,15 @@ __global__ __launch_bounds__(TILE / PHASE_V) void k_phase_buf(PhaseArgs p, StepA
         if constexpr (COLOUR_NSUM) {
             buf_store_raw_nt<sizeof(C)>(__builtin_bit_cast(CB, (C)tot), make_rsrc(p.nab, npad * esz), s[v] * esz, 0u);
         } else {
-            buf_store_raw_nt<PB>(__builtin_bit_cast(typename RawBits<PB>::type, C2{(C)na, (C)nb}),
-                                 make_rsrc(p.nab, npad * (uint32_t)PB), s[v] * (uint32_t)PB, 0u);
+            buf_store_pair_nt<C>(make_rsrc(p.nab, npad * (uint32_t)PB), s[v], 0u, (C)na, (C)nb);
         }
         buf_store_raw_nt<sizeof(C)>(__builtin_bit_cast(CB, (C)(tot != (R)0 ? (na - nb) / tot : (R)0)), rph,
                                     s[v] * esz, 0u);
         if (p.st->omega == 0.0) {
             // testing aid (collision off): keep the streamed colours
 #pragma unroll
-            for (int q = 0; q < 7; ++q) ((C2 *)p.about)[(int64_t)q * npad + s[v]] = C2{(C)av[v][q], (C)bv[v][q]};
+            for (int q = 0; q < 7; ++q)
+                store_pair<C>(&((C2 *)p.about)[(int64_t)q * npad + s[v]], (C)av[v][q], (C)bv[v][q], false);
         }
     }
 }
@@ -610,20 +657,32 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
     const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
     const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
     const uint32_t sent = 19u * npad, pos = threadIdx.x;
+    // FORM_RUN: a tile of 8-bit codes read as run codes (see pull_format.h)
+    constexpr int FORM_RUN = 3;
     auto gather = [&](auto form_tag) {
         constexpr int FORM = decltype(form_tag)::value;
+        constexpr int CODES = FORM == FORM_RUN ? PULL_TILE_BYTE : FORM;
         uint32_t w[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, tail = 0;
-        load_pull_words<FORM, 18>(a, s, npad, w, tail);
+        RunWave rw{0u, 0u, 0u, false};
+        uint32_t off = 0;
+        if constexpr (FORM == FORM_RUN) {
+            const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.pull_runs, a.runs_bytes);
+            rw = load_runs(rr, s);
+            load_runs_wide(rw, rr, s, npad);
+        } else {
+            load_pull_words<FORM, 18>(a, s, npad, w, tail);
+        }
         const __amdgpu_buffer_rsrc_t rn = make_rsrc(nbr, a.nbr_bytes);
 #pragma unroll
         for (int q = 1; q < 19; ++q) {
             const uint32_t code = FORM == PULL_TILE_INT32
                                       ? (uint32_t)buf_load_raw<4, SC_IDX_AUX>(rn, s * 4u, (uint32_t)(q - 1) * npad * 4u)
-                                      : pull_code<FORM>(w, tail, q);
+                                  : FORM == FORM_RUN ? run_code(rw, q, off)
+                                                     : pull_code<CODES>(w, tail, q);
             int kind;
             const uint32_t base = FORM == PULL_TILE_INT32 ? 0u : (uint32_t)hdr[q - 1];
-            const uint32_t idx = decode_pull<FORM>(code, base, pos, (uint32_t)d3q19::opp(q) * npad + s, sent,
-                                                   (uint32_t)q, npad, kind);
+            const uint32_t idx = decode_pull<CODES>(code, base, pos, (uint32_t)d3q19::opp(q) * npad + s, sent,
+                                                    (uint32_t)q, npad, kind);
             g[q] = Codec<T>::dec(__builtin_bit_cast(T, buf_load_raw<sizeof(T)>(rf, idx * fsz, 0u)), q);
             const uint32_t src = kind == PULL_REG ? idx - (uint32_t)q * npad : s;
             const R pv = (R)__builtin_bit_cast(C, buf_load_raw<sizeof(C)>(rph, src * esz, 0u));
@@ -634,7 +693,12 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
             if (d3q19::cz[q]) gz -= d3q19::cz[q] * w3 * ph;
         }
     };
-    if (form == PULL_TILE_BYTE)
+    // run codes where the table has them, except in FP16 storage (the same
+    // rule and reason as the single-fluid step: 2 % off the FP32 colour
+    // step, 3 % onto the FP16 one)
+    if (form == PULL_TILE_BYTE && !std::is_same<T, _Float16>::value && a.pull_runs && hdr[PULL_HDR_RUNS])
+        gather(std::integral_constant<int, FORM_RUN>{});
+    else if (form == PULL_TILE_BYTE)
         gather(std::integral_constant<int, PULL_TILE_BYTE>{});
     else if (form == PULL_TILE_HALF)
         gather(std::integral_constant<int, PULL_TILE_HALF>{});
@@ -698,7 +762,6 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
         }
         const R bab = (R)c.beta * na * nb;
         const __amdgpu_buffer_rsrc_t rabo = make_rsrc(c.about, 7u * npad * (uint32_t)PB);
-        typedef typename RawBits<PB>::type CB2;
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
             R cu = 0, cn = 0;
@@ -716,8 +779,8 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
             }
             const R w = (R)d3q19::weight7(q);
             const R adv = (R)1 + (R)4.5 * cu;
-            const C2 v = {(C)(w * (na * adv + bab * cn)), (C)(w * (nb * adv - bab * cn))};
-            buf_store_raw_nt<PB>(__builtin_bit_cast(CB2, v), rabo, s * (uint32_t)PB, (uint32_t)q * npad * (uint32_t)PB);
+            buf_store_pair_nt<C>(rabo, s, (uint32_t)q * npad * (uint32_t)PB, (C)(w * (na * adv + bab * cn)),
+                                 (C)(w * (nb * adv - bab * cn)));
         }
     }
 

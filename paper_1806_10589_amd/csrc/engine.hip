@@ -72,7 +72,7 @@ struct flbm_ctx {
     // compact pull table (buffer path)
     CompactPull pull;
     int pull_format = FLBM_PULL_INT32;
-    uint32_t *pull_codes = nullptr, *pull_bytes = nullptr;
+    uint32_t *pull_codes = nullptr, *pull_bytes = nullptr, *pull_runs = nullptr;
     int32_t *pull_hdr = nullptr;
     DevState *st = nullptr;
     double *kpart = nullptr, *bpart_in = nullptr, *bpart_out = nullptr, *spart = nullptr;
@@ -154,6 +154,12 @@ size_t pull_bytes_size(const flbm_ctx *c)
     return c->pull.bytes.size() * sizeof(uint32_t) + c->pull.tail.size() * sizeof(uint16_t);
 }
 
+// run codes: [n_pad][2] words, then the [n_pad] second words
+size_t pull_runs_size(const flbm_ctx *c)
+{
+    return (c->pull.runs.size() + c->pull.runs_hi.size()) * sizeof(uint32_t);
+}
+
 flbm_status upload_pull(flbm_ctx *c)
 {
     HIPCHK(c, hipMemcpyAsync(c->pull_codes, c->pull.codes.data(), c->pull.codes.size() * sizeof(uint32_t),
@@ -162,6 +168,10 @@ flbm_status upload_pull(flbm_ctx *c)
                              hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync((char *)c->pull_bytes + c->pull.bytes.size() * sizeof(uint32_t), c->pull.tail.data(),
                              c->pull.tail.size() * sizeof(uint16_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pull_runs, c->pull.runs.data(), c->pull.runs.size() * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->pull_runs + c->pull.runs.size(), c->pull.runs_hi.data(),
+                             c->pull.runs_hi.size() * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->pull_hdr, c->pull.hdr.data(), c->pull.hdr.size() * sizeof(int32_t),
                              hipMemcpyHostToDevice, c->stream));
     return FLBM_OK;
@@ -185,6 +195,7 @@ size_t carve(flbm_ctx *c, char *base)
     char *pcw = c->pull.tiles ? take(c->pull.codes.size() * sizeof(uint32_t)) : nullptr;
     char *pcb = c->pull.tiles ? take(pull_bytes_size(c)) : nullptr;
     char *pch = c->pull.tiles ? take(c->pull.hdr.size() * sizeof(int32_t)) : nullptr;
+    char *pcr = c->pull.tiles ? take(pull_runs_size(c)) : nullptr;
     char *st = take(sizeof(DevState));
     char *kp = take(PLANE_MAX_BLOCKS * sizeof(double));
     char *bi = take((size_t)std::max(1, c->nt_in) * sizeof(double));
@@ -215,6 +226,7 @@ size_t carve(flbm_ctx *c, char *base)
         c->pull_codes = (uint32_t *)pcw;
         c->pull_bytes = (uint32_t *)pcb;
         c->pull_hdr = (int32_t *)pch;
+        c->pull_runs = (uint32_t *)pcr;
         c->st = (DevState *)st;
         c->kpart = (double *)kp;
         c->bpart_in = (double *)bi;
@@ -264,6 +276,9 @@ StepArgs step_args(const flbm_ctx *c)
     a.pull_hdr = compact ? c->pull_hdr : nullptr;
     a.codes_bytes = compact ? (uint32_t)(c->pull.codes.size() * sizeof(uint32_t)) : 0u;
     a.bytes_bytes = compact ? (uint32_t)pull_bytes_size(c) : 0u;
+    const bool runs = compact && c->pull_format == FLBM_PULL_RUN && c->pull.tiles_run > 0;
+    a.pull_runs = runs ? c->pull_runs : nullptr;
+    a.runs_bytes = runs ? (uint32_t)pull_runs_size(c) : 0u;
     a.flux_mode = flux;
     a.rho0 = c->p.rho0;
     a.inv_rho0 = 1.0 / c->p.rho0;
@@ -518,7 +533,10 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
         if (np >= 2 && e <= c.release_tol) st->ctrl_released = 1u;
         // progress judge: the error must fall by 10 % within stall_decisions decisions
         if (n == 0 || e < 0.9 * st->ctrl_best) {
+            // two 8-byte stores (a merged 16-byte store is avoided, see
+            // store_pair in colour.h)
             st->ctrl_best = e;
+            __asm__ __volatile__("" ::: "memory");
             st->ctrl_best_n = n;
         } else if (c.stall_decisions > 0 && n - st->ctrl_best_n >= c.stall_decisions) {
             st->ctrl_released = 1u;
@@ -535,13 +553,17 @@ __global__ __launch_bounds__(256) void k_controller(CtrlArgs c)
                         !(c.relative && !(drho > 0.0)) && limit > 0.0;
         double delta = 0.0;
         if (on) delta = fmin(limit, fmax(-limit, c.gain * (rho_hat - rho_plain)));
+        // 8-byte stores, kept apart (as above)
         st->ctrl_rho = on ? rho_hat : 0.0;
+        __asm__ __volatile__("" ::: "memory");
         st->ctrl_limit = on ? limit : 0.0;
+        __asm__ __volatile__("" ::: "memory");
         st->ctrl_gain = c.gain;
         st->ctrl_on = on ? 1u : 0u;
         st->ctrl_delta = delta;
+        __asm__ __volatile__("" ::: "memory");
         st->ctrl_steps = n + 1;
-        double *aux = (double *)(rec + 32);
+        volatile double *aux = (double *)(rec + 32);
         aux[0] = drho;
         aux[1] = rho_plain;
         aux[2] = (double)y;
@@ -797,7 +819,7 @@ flbm_status flbm_create(const uint8_t *solid_mask, const flbm_params *p, void *h
             delete c;
             return FLBM_EINVAL;
         }
-        c->pull_format = FLBM_PULL_COMPACT;
+        c->pull_format = FLBM_PULL_RUN;
     }
     c->blocks256 = (int)(c->lat.n_pad / BLOCK);
     c->obs_slots = std::max(c->tiles, c->blocks256);
@@ -975,14 +997,16 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr)
 flbm_status flbm_set_pull_format(flbm_ctx *c, int32_t format, int32_t limit16, int32_t limit8)
 {
     if (!c) return FLBM_EINVAL;
-    if (format != FLBM_PULL_INT32 && format != FLBM_PULL_HALF && format != FLBM_PULL_COMPACT)
+    if (format != FLBM_PULL_INT32 && format != FLBM_PULL_HALF && format != FLBM_PULL_COMPACT &&
+        format != FLBM_PULL_RUN)
         return fail(c, FLBM_EINVAL, "unknown pull format");
     if (limit16 < 0 || (uint32_t)limit16 > PULL_MAX_CODE || limit8 < 0 || (uint32_t)limit8 > PULL_MAX_BYTE)
         return fail(c, FLBM_EINVAL, "code limit out of range");
     if (format != FLBM_PULL_INT32 && !c->pull.tiles)
         return fail(c, FLBM_ESTATE, "no compact pull table (a lattice past the 4 GiB buffer path)");
     const int32_t l16 = limit16 ? limit16 : (int32_t)PULL_MAX_CODE;
-    const int32_t l8 = format == FLBM_PULL_COMPACT ? (limit8 ? limit8 : (int32_t)PULL_MAX_BYTE) : 0;
+    const bool bytes_on = format == FLBM_PULL_COMPACT || format == FLBM_PULL_RUN;
+    const int32_t l8 = bytes_on ? (limit8 ? limit8 : (int32_t)PULL_MAX_BYTE) : 0;
     if (c->ready) {
         HIPCHK(c, hipSetDevice(c->device));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1012,6 +1036,23 @@ flbm_status flbm_pull_format_info(const flbm_ctx *c, int32_t *format, int64_t *t
     if (tiles8) *tiles8 = on ? c->pull.tiles8 : 0;
     if (tiles16) *tiles16 = on ? c->pull.tiles16 : 0;
     if (tiles) *tiles = c->tiles;
+    return FLBM_OK;
+}
+
+flbm_status flbm_pull_run_info(const flbm_ctx *c, int64_t *tiles_run, int64_t *waves_wide)
+{
+    if (!c) return FLBM_EINVAL;
+    if (tiles_run) *tiles_run = c->pull.tiles ? c->pull.tiles_run : 0;
+    if (waves_wide) *waves_wide = c->pull.tiles ? c->pull.waves_wide : 0;
+    return FLBM_OK;
+}
+
+flbm_status flbm_get_pull_runs(const flbm_ctx *c, uint32_t *runs, uint32_t *runs_hi)
+{
+    if (!c) return FLBM_EINVAL;
+    if (!c->pull.tiles) return fail(const_cast<flbm_ctx *>(c), FLBM_ESTATE, "no compact pull table");
+    if (runs) std::memcpy(runs, c->pull.runs.data(), c->pull.runs.size() * sizeof(uint32_t));
+    if (runs_hi) std::memcpy(runs_hi, c->pull.runs_hi.data(), c->pull.runs_hi.size() * sizeof(uint32_t));
     return FLBM_OK;
 }
 
@@ -1518,6 +1559,7 @@ struct flbm_batch {
     int device = 0;
     bool use_buf = false;
     int precision = 0, model = 0;
+    bool tile8_ok = false;  // the 64-VGPR tile kernel of this batch runs without scratch
     flbm_schedule sched{};
     BatchSample *d_tab = nullptr;
     BatchItem *d_work = nullptr;
@@ -1612,6 +1654,29 @@ flbm_status batch_refresh(flbm_batch *b)
     return FLBM_OK;
 }
 
+// Whether the 64-VGPR tile kernel (the step without observables) of this
+// precision, model and address path fits its budget without scratch. Where
+// it spills it is not used: besides the cost of scratch, register spills are
+// 16-byte stores whose registers are reused at once, the order that has
+// stored wrong values on gfx950 (see store_pair in colour.h).
+template <typename T, bool MRT>
+bool tile8_fits(bool use_buf)
+{
+    hipFuncAttributes fa{};
+    const hipError_t e = use_buf ? hipFuncGetAttributes(&fa, (const void *)k_batch_tile8<T, false, true, MRT>)
+                                 : hipFuncGetAttributes(&fa, (const void *)k_batch_tile8<T, false, false, MRT>);
+    return e == hipSuccess && fa.localSizeBytes == 0;
+}
+
+bool batch_tile8_fits(const flbm_batch *b)
+{
+    const bool mrt = b->model == FLBM_MRT;
+    if (b->precision == FLBM_FP64) return mrt ? tile8_fits<double, true>(b->use_buf) : tile8_fits<double, false>(b->use_buf);
+    if (b->precision == FLBM_FP16DEV)
+        return mrt ? tile8_fits<_Float16, true>(b->use_buf) : tile8_fits<_Float16, false>(b->use_buf);
+    return mrt ? tile8_fits<float, true>(b->use_buf) : tile8_fits<float, false>(b->use_buf);
+}
+
 template <typename T, bool MRT>
 void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
 {
@@ -1622,7 +1687,7 @@ void batch_launch_t(flbm_batch *b, hipStream_t s, int parity, bool obs)
         // 64 VGPRs it spills to scratch, and a scratch-using launch inside a
         // captured chunk costs far more than the step itself.
         const dim3 g(b->n_work), blk(SC_BLOCK);
-        const bool o8 = b->sched.occupancy == 8 && !obs;
+        const bool o8 = b->sched.occupancy == 8 && !obs && b->tile8_ok;
 #define FLBM_BATCH_TILE(OB, BU)                                                                           \
     do {                                                                                                  \
         if (o8)                                                                                           \
@@ -1739,6 +1804,8 @@ flbm_status flbm_batch_create(int32_t n, flbm_ctx *const *samples, flbm_batch **
     b->precision = c0->p.precision;
     b->model = c0->p.model;
     b->sched = flbm_schedule{0, FLBM_ORDER_INTERLEAVE, 4, 64, 0};
+    (void)hipSetDevice(b->device);
+    b->tile8_ok = batch_tile8_fits(b);
     if (hipSetDevice(b->device) != hipSuccess || hipMalloc(&b->d_tab, n * sizeof(BatchSample)) != hipSuccess) {
         delete b;
         return FLBM_ENOMEM;
@@ -1869,12 +1936,13 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
     const int prec = b->precision;
     // the collision model and the pull-table formats in use change the
     // kernels, so they are part of the key: bit 0 int32 table, bit 1 16-bit
-    // codes, bit 2 compact (8- and 16-bit) codes
+    // codes, bit 2 compact (8- and 16-bit) codes, bit 3 compact codes with
+    // run codes
     const int model = b->s.empty() ? 0 : b->s[0]->p.model;
     int formats = 0;
     for (flbm_ctx *c : b->s) {
         const bool coded = c->use_buf && c->pull.tiles > 0 && c->pull_format != FLBM_PULL_INT32;
-        formats |= coded ? (c->pull_format == FLBM_PULL_HALF ? 2 : 4) : 1;
+        formats |= !coded ? 1 : c->pull_format == FLBM_PULL_HALF ? 2 : c->pull_format == FLBM_PULL_COMPACT ? 4 : 8;
     }
     const int chunk = b->sched.chunk;
     // a cached choice for this architecture, precision, model, formats and
@@ -1915,6 +1983,7 @@ flbm_status flbm_batch_autotune(flbm_batch *b, const char *cache_path, int32_t t
             for (int t : tpis)
                 for (int occ : {0, 8}) {
                     if (occ == 8 && !(g == 0 && t == 1)) continue;  // a budget only the loop-free kernel has
+                    if (occ == 8 && !b->tile8_ok) continue;         // that kernel spills here
                     flbm_schedule s{g, o, t, chunk, occ};
                     flbm_status rc = flbm_batch_set_schedule(b, &s);
                     if (rc) return rc;

@@ -130,7 +130,9 @@ struct StepArgs {
     const uint32_t *pull_codes;     // compact pull table: 16-bit codes ([9][npad] words)
     const uint32_t *pull_bytes;     // byte codes ([4][npad] words, then [npad] 16-bit)
     const int32_t *pull_hdr;        // per-tile header ([tiles][PULL_HDR]); null: int32 table only
-    uint32_t codes_bytes, bytes_bytes;  // sizes of the two code arrays for the descriptors
+    const uint32_t *pull_runs;      // run codes ([npad][2] words, then [npad]); null: byte codes only
+    uint32_t codes_bytes, bytes_bytes;  // sizes of the code arrays for the descriptors
+    uint32_t runs_bytes, pad2_;
 };
 
 struct PlaneArgs {
@@ -635,14 +637,17 @@ __device__ __forceinline__ void finalize_step(const StepArgs &a, const int rd)
     if (threadIdx.x == 0) {
         DevState *st = a.st;
         const int64_t t = st->step;
-        double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
+        // volatile: one 8-byte store each (see store_pair in colour.h)
+        volatile double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
         if (a.flux_mode) {
             h[0] = 1.0 + inlet_drho(st, rd, a.rho0, a.a_in);
             h[1] = ti;
             h[2] = to;
             st->s_carry[rd ^ 1] = tn;
         } else {
-            h[0] = h[1] = h[2] = __builtin_nan("");
+            h[0] = __builtin_nan("");
+            h[1] = __builtin_nan("");
+            h[2] = __builtin_nan("");
         }
         h[3] = __builtin_nan("");
         h[4] = __builtin_nan("");
@@ -745,6 +750,47 @@ __device__ __forceinline__ void load_byte_codes(__amdgpu_buffer_rsrc_t rb, uint3
     buf_load_v<V, uint16_t, uint16_t, SC_IDX_AUX>(rb, s0 * 2u, 16u * npad, tl);
 }
 
+// Run codes of a 64-site wave, one site per lane (see pull_format.h): this
+// lane's mask and its words of the wave's list of changed codes.
+struct RunWave {
+    uint32_t mask, w0, w1;
+    bool wide;  // the list is longer than 256 bytes (the same on every lane)
+};
+
+__device__ __forceinline__ RunWave load_runs(__amdgpu_buffer_rsrc_t rr, uint32_t s)
+{
+    const auto x = buf_load_raw<8, SC_IDX_AUX>(rr, s * 8u, 0u);
+    return RunWave{x[0], x[1], 0u, false};
+}
+
+// The second word of the list, for the waves that have one (a branch taken
+// by the whole wave).
+__device__ __forceinline__ void load_runs_wide(RunWave &r, __amdgpu_buffer_rsrc_t rr, uint32_t s, uint32_t npad)
+{
+    r.wide = (__builtin_amdgcn_readfirstlane(r.mask) & PULL_RUN_WIDE) != 0u;
+    if (r.wide) r.w1 = buf_load_raw<4, SC_IDX_AUX>(rr, s * 4u, 8u * npad);
+}
+
+// Byte code of direction q from the wave's run codes; directions are taken
+// in order 1..18 with off (0 before direction 1) counting the listed codes
+// of the directions before q. Entry k of the list sits in byte k % 4 of
+// lane (k / 4) % 64's first (k < 256) or second word.
+__device__ __forceinline__ uint32_t run_code(const RunWave &r, int q, uint32_t &off)
+{
+    const uint32_t e = (r.mask >> (q - 1)) & 1u;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(e != 0u);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const uint32_t k = off + below + e - 1u;  // the wave's first site lists every direction
+    off += (uint32_t)__builtin_popcountll(m);
+    const int addr = (int)(k & 0xFCu);
+    uint32_t d = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)r.w0);
+    if (r.wide) {
+        const uint32_t d1 = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)r.w1);
+        d = k >= 256u ? d1 : d;
+    }
+    return (d >> ((k & 3u) * 8u)) & 0xFFu;
+}
+
 // The work of one tile (SC_BLOCK threads), shared by the single-lattice
 // kernel (one tile per block) and the batched kernel (a work list of tiles
 // of many lattices per block).
@@ -774,40 +820,61 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
             for (int v = 0; v < V; ++v) g[v][0] = load_pop<T, SCALED>(r[v], 0);
         }
         const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
-        // FP16 loads the byte codes before the tile's form is known, so that
-        // their latency overlaps the header's (wasted on the few tiles of
-        // another form, whose byte rows are zero): 6 % off the FP16 step,
-        // which waits on latency, and 1 % onto the FP32 step and the colour
-        // passes, which wait on bandwidth
+        // FP16 loads the codes (run codes where the table has them, else
+        // byte codes) before the tile's form is known, so that their latency
+        // overlaps the header's (wasted on the few tiles of another form):
+        // 6 % off the FP16 step, which waits on latency, and 1 % onto the
+        // FP32 step and the colour passes, which wait on bandwidth
         constexpr bool SPEC = std::is_same<T, _Float16>::value;
+        // run codes: one site per lane, where the table carries them, and not
+        // in FP16, whose step waits on latency: decoding them (a ballot, a
+        // lane count and a cross-lane read per direction) made it 3 % slower,
+        // while the 10 bytes per site they save take 4 % off the FP32 step,
+        // which waits on bandwidth
+        const bool runs_on = V == 1 && !SPEC && a.pull_runs != nullptr;
+        const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.pull_runs, a.runs_bytes);
         uint32_t w[4][V];
         uint16_t tl[V];
+        RunWave rw{0u, 0u, 0u, false};
         if constexpr (SPEC) {
-            if (hdr) load_byte_codes<V>(make_rsrc(a.pull_bytes, a.bytes_bytes), (uint32_t)s0, (uint32_t)npad, w, tl);
+            if (hdr) {
+                if (runs_on)
+                    rw = load_runs(rr, (uint32_t)s0);
+                else
+                    load_byte_codes<V>(make_rsrc(a.pull_bytes, a.bytes_bytes), (uint32_t)s0, (uint32_t)npad, w, tl);
+            }
         }
         const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
         const uint32_t sent = 19u * (uint32_t)npad;
         // position of each of this thread's sites in the tile
         const uint32_t p0 = (uint32_t)(s0 - (int64_t)tile * TILE);
-        if (form == PULL_TILE_BYTE) {
+        // byte code c of direction q: flat index = base + position + code
+        auto pull_byte = [&](int q, int v, uint32_t c) {
+            const uint32_t base = (uint32_t)hdr[q - 1];
+            const uint32_t bb = (uint32_t)d3q19::opp(q) * (uint32_t)npad + (uint32_t)s0;
+            const uint32_t idx = c <= PULL_MAX_BYTE ? base + p0 + (uint32_t)v + c
+                                 : (c == PULL_BYTE_BOUNCE ? bb + (uint32_t)v : sent);
+            T r[1];
+            buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
+            g[v][q] = load_pop<T, SCALED>(r[0], q);
+        };
+        if (form == PULL_TILE_BYTE && runs_on && hdr[PULL_HDR_RUNS]) {
+            if constexpr (!SPEC) rw = load_runs(rr, (uint32_t)s0);
+            load_runs_wide(rw, rr, (uint32_t)s0, (uint32_t)npad);
+            uint32_t off = 0;
+#pragma unroll
+            for (int q = 1; q < 19; ++q) pull_byte(q, 0, run_code(rw, q, off));
+        } else if (form == PULL_TILE_BYTE) {
             // byte codes: directions 1..16 in four words, 17 and 18 in a
-            // 16-bit tail; flat index = base + position + code
-            if constexpr (!SPEC)
+            // 16-bit tail
+            if (!SPEC || runs_on)
                 load_byte_codes<V>(make_rsrc(a.pull_bytes, a.bytes_bytes), (uint32_t)s0, (uint32_t)npad, w, tl);
 #pragma unroll
             for (int q = 1; q < 19; ++q) {
-                const uint32_t base = (uint32_t)hdr[q - 1];
-                const uint32_t bb = (uint32_t)d3q19::opp(q) * (uint32_t)npad + (uint32_t)s0;
 #pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const uint32_t c = q <= 16 ? (w[(q - 1) >> 2][v] >> (((q - 1) & 3) * 8)) & 0xFFu
-                                               : ((uint32_t)tl[v] >> ((q - 17) * 8)) & 0xFFu;
-                    const uint32_t idx = c <= PULL_MAX_BYTE ? base + p0 + (uint32_t)v + c
-                                         : (c == PULL_BYTE_BOUNCE ? bb + (uint32_t)v : sent);
-                    T r[1];
-                    buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
-                    g[v][q] = load_pop<T, SCALED>(r[0], q);
-                }
+                for (int v = 0; v < V; ++v)
+                    pull_byte(q, v, q <= 16 ? (w[(q - 1) >> 2][v] >> (((q - 1) & 3) * 8)) & 0xFFu
+                                            : ((uint32_t)tl[v] >> ((q - 17) * 8)) & 0xFFu);
             }
         } else if (form == PULL_TILE_HALF) {
             // 16-bit codes, two per word; flat index = base + code
@@ -1095,7 +1162,7 @@ __global__ __launch_bounds__(OBS_BLOCK) void k_obs_finalize(ObsArgs a)
         st->obs_umax = umax;
         st->obs_bad = bb;
         if (a.to_history) {
-            double *h = a.hist + ((st->step - 1) % a.hist_cap) * HIST_STRIDE;
+            volatile double *h = a.hist + ((st->step - 1) % a.hist_cap) * HIST_STRIDE;
             h[3] = mass;
             h[4] = umax;
             if (a.obs_na) {

@@ -205,6 +205,53 @@ uint32_t code_of(const Lattice &L, int q, int64_t s, int64_t base, int64_t p, in
     return e == L.sentinel ? PULL_UNKNOWN : bounce ? PULL_BOUNCE : (uint32_t)(e - base);
 }
 
+uint32_t byte_code(const CompactPull &cp, int q, int64_t s, int64_t npad)
+{
+    return q <= 16 ? (cp.bytes[(size_t)((q - 1) >> 2) * npad + s] >> (((q - 1) & 3) * 8)) & 0xFFu
+                   : ((uint32_t)cp.tail[s] >> ((q - 17) * 8)) & 0xFFu;
+}
+
+// Run codes of the byte tile starting at s0 (see pull_format.h); false, with
+// nothing written, if a wave would list more than PULL_RUN_MAX codes.
+bool build_runs(CompactPull &cp, int64_t s0, int tile, int64_t npad, int64_t &wide)
+{
+    std::vector<uint8_t> list(PULL_RUN_MAX);
+    std::vector<uint32_t> mask(PULL_RUN_WAVE), lo(PULL_RUN_WAVE), hi(PULL_RUN_WAVE);
+    std::vector<uint32_t> out_lo((size_t)tile * 2), out_hi((size_t)tile);
+    int64_t nwide = 0;
+    for (int w = 0; w < tile / PULL_RUN_WAVE; ++w) {
+        const int64_t sw = s0 + (int64_t)w * PULL_RUN_WAVE;
+        std::fill(mask.begin(), mask.end(), 0u);
+        int e = 0;
+        for (int q = 1; q < 19; ++q)
+            for (int l = 0; l < PULL_RUN_WAVE; ++l) {
+                const uint32_t c = byte_code(cp, q, sw + l, npad);
+                if (l > 0 && c == byte_code(cp, q, sw + l - 1, npad)) continue;
+                if (e == PULL_RUN_MAX) return false;
+                mask[l] |= 1u << (q - 1);
+                list[e++] = (uint8_t)c;
+            }
+        std::fill(list.begin() + e, list.end(), (uint8_t)0);
+        const bool wide_w = e > 4 * PULL_RUN_WAVE;
+        nwide += wide_w;
+        for (int l = 0; l < PULL_RUN_WAVE; ++l) {
+            uint32_t b0 = 0, b1 = 0;
+            for (int j = 0; j < 4; ++j) {
+                b0 |= (uint32_t)list[4 * l + j] << (8 * j);
+                b1 |= (uint32_t)list[4 * PULL_RUN_WAVE + 4 * l + j] << (8 * j);
+            }
+            const size_t i = (size_t)w * PULL_RUN_WAVE + l;
+            out_lo[2 * i] = mask[l] | (wide_w ? PULL_RUN_WIDE : 0u);
+            out_lo[2 * i + 1] = b0;
+            out_hi[i] = b1;
+        }
+    }
+    std::copy(out_lo.begin(), out_lo.end(), cp.runs.begin() + 2 * s0);
+    std::copy(out_hi.begin(), out_hi.end(), cp.runs_hi.begin() + s0);
+    wide = nwide;
+    return true;
+}
+
 }  // namespace
 
 std::string build_compact_pull(const Lattice &L, int tile, int32_t limit16, int32_t limit8, CompactPull &cp)
@@ -221,6 +268,8 @@ std::string build_compact_pull(const Lattice &L, int tile, int32_t limit16, int3
         cp.codes.assign((size_t)9 * npad, 0u);
         cp.bytes.assign((size_t)4 * npad, 0u);
         cp.tail.assign((size_t)npad, 0);
+        cp.runs.assign((size_t)2 * npad, 0u);
+        cp.runs_hi.assign((size_t)npad, 0u);
         cp.hdr.assign((size_t)cp.tiles * PULL_HDR, 0);
     } catch (const std::bad_alloc &) {
         return "host allocation failed while building the compact pull table";
@@ -258,13 +307,22 @@ std::string build_compact_pull(const Lattice &L, int tile, int32_t limit16, int3
                     }
                 }
             }
+            int64_t wide = 0;
+            if (form == PULL_TILE_BYTE && tile % PULL_RUN_WAVE == 0 && build_runs(cp, s0, tile, npad, wide))
+                h[PULL_HDR_RUNS] = 1 + (int32_t)wide;  // reduced to the flag below
         }
     });
-    cp.tiles16 = cp.tiles8 = 0;
+    cp.tiles16 = cp.tiles8 = cp.tiles_run = cp.waves_wide = 0;
     for (int64_t t = 0; t < cp.tiles; ++t) {
-        const int f = cp.hdr[t * PULL_HDR + PULL_HDR_FORM];
+        int32_t *h = cp.hdr.data() + t * PULL_HDR;
+        const int f = h[PULL_HDR_FORM];
         cp.tiles16 += f == PULL_TILE_HALF;
         cp.tiles8 += f == PULL_TILE_BYTE;
+        if (h[PULL_HDR_RUNS]) {
+            cp.tiles_run += 1;
+            cp.waves_wide += h[PULL_HDR_RUNS] - 1;
+            h[PULL_HDR_RUNS] = 1;
+        }
     }
     return std::string();
 }
@@ -276,7 +334,37 @@ std::string check_compact_pull(const Lattice &L, const CompactPull &cp)
     for (int64_t t = 0; t < cp.tiles; ++t) {
         const int32_t *h = cp.hdr.data() + t * PULL_HDR;
         const int form = h[PULL_HDR_FORM];
-        if (form < PULL_TILE_INT32 || form > PULL_TILE_BYTE || h[19] != 0) return "bad compact tile header";
+        if (form < PULL_TILE_INT32 || form > PULL_TILE_BYTE || h[PULL_HDR_RUNS] < 0 || h[PULL_HDR_RUNS] > 1 ||
+            (h[PULL_HDR_RUNS] && form != PULL_TILE_BYTE))
+            return "bad compact tile header";
+        if (h[PULL_HDR_RUNS]) {
+            // decode the run codes as the step kernel does, lane by lane
+            for (int64_t sw = t * cp.tile; sw < (t + 1) * cp.tile; sw += PULL_RUN_WAVE) {
+                const bool wide = (cp.runs[(size_t)2 * sw] & PULL_RUN_WIDE) != 0;
+                int64_t off = 0;
+                for (int q = 1; q < 19; ++q) {
+                    int64_t below = 0;
+                    for (int l = 0; l < PULL_RUN_WAVE; ++l) {
+                        const uint32_t m = cp.runs[(size_t)2 * (sw + l)];
+                        if (((m & PULL_RUN_WIDE) != 0) != wide || (m & ~PULL_RUN_WIDE) >> 18) return "bad run mask";
+                        const int64_t e = (m >> (q - 1)) & 1u;
+                        if (l == 0 && !e) return "run codes without a wave start";
+                        const int64_t k = off + below + e - 1;
+                        below += e;
+                        if (k >= (wide ? 2 : 1) * 4 * PULL_RUN_WAVE) return "run list too long";
+                        const uint32_t word = k < 4 * PULL_RUN_WAVE ? cp.runs[(size_t)2 * (sw + k / 4) + 1]
+                                                                   : cp.runs_hi[(size_t)(sw + (k - 4 * PULL_RUN_WAVE) / 4)];
+                        if (((word >> (8 * (k & 3))) & 0xFFu) != byte_code(cp, q, sw + l, npad))
+                            return "run code decodes wrongly";
+                    }
+                    off += below;
+                }
+            }
+        } else {
+            for (int64_t s = t * cp.tile; s < (t + 1) * cp.tile; ++s)
+                if (cp.runs[(size_t)2 * s] || cp.runs[(size_t)2 * s + 1] || cp.runs_hi[(size_t)s])
+                    return "run codes in a tile without the run flag";
+        }
         for (int64_t p = 0; p < cp.tile; ++p) {
             const int64_t s = t * cp.tile + p;
             bool zero16 = true, zero8 = cp.tail[s] == 0;

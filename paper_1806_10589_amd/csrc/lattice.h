@@ -45,9 +45,12 @@ struct CompactPull {
     int tile = 0;
     int32_t limit16 = 0, limit8 = 0;  // largest regular code of each form (0: form not used)
     int64_t tiles = 0, tiles16 = 0, tiles8 = 0;
+    int64_t tiles_run = 0, waves_wide = 0;  // byte tiles with run codes; their waves listing > 256 codes
     std::vector<uint32_t> codes;   // [9][n_pad] 16-bit codes
     std::vector<uint32_t> bytes;   // [4][n_pad] byte codes of directions 1..16
     std::vector<uint16_t> tail;    // [n_pad] byte codes of directions 17 (low) and 18 (high)
+    std::vector<uint32_t> runs;    // [n_pad][2] run codes: mask, list bytes 4l..4l+3
+    std::vector<uint32_t> runs_hi; // [n_pad] list bytes 256+4l..256+4l+3
     std::vector<int32_t> hdr;      // [tiles][PULL_HDR]
 };
 
@@ -55,7 +58,9 @@ struct CompactPull {
 // (n_pad must be a multiple): each tile takes byte codes if its sources fit
 // limit8 (0 <= limit8 <= PULL_MAX_BYTE; 0 turns byte codes off), else
 // 16-bit codes if they fit limit16 (1 <= limit16 <= PULL_MAX_CODE), else
-// the int32 table. Returns "" on success.
+// the int32 table. Byte tiles whose waves all list at most PULL_RUN_MAX
+// codes also get run codes (see pull_format.h) and the header's run flag.
+// Returns "" on success.
 std::string build_compact_pull(const Lattice &L, int tile, int32_t limit16, int32_t limit8, CompactPull &out);
 
 // Every entry of every coded tile decodes to the int32 table's entry, and

@@ -29,7 +29,7 @@ FLBM_ESCRATCH = -9
 FLBM_FP64, FLBM_FP32, FLBM_FP16DEV = 0, 1, 2
 FLBM_BGK, FLBM_COLOUR, FLBM_MRT = 0, 1, 2
 FLBM_Z_FLUX, FLBM_Z_PERIODIC, FLBM_Z_WALL = 0, 1, 2
-FLBM_PULL_INT32, FLBM_PULL_HALF, FLBM_PULL_COMPACT = 0, 1, 2
+FLBM_PULL_INT32, FLBM_PULL_HALF, FLBM_PULL_COMPACT, FLBM_PULL_RUN = 0, 1, 2, 3
 PULL_HDR = 20  # int32 header entries per tile of the compact pull table
 
 PRECISIONS = {"fp64": FLBM_FP64, "fp32": FLBM_FP32, "fp16dev": FLBM_FP16DEV}
@@ -111,6 +111,8 @@ _SIGS = {
     "flbm_set_pull_format": [_P, _I32, _I32, _I32],
     "flbm_pull_format_info": [_P, ctypes.POINTER(_I32), _I64P, _I64P, _I64P],
     "flbm_get_compact_pull": [_P, _P, _P, _P, _P],
+    "flbm_pull_run_info": [_P, _I64P, _I64P],
+    "flbm_get_pull_runs": [_P, _P, _P],
     "flbm_state_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
     "flbm_save_state": [_P, _P, ctypes.c_size_t],
     "flbm_load_state": [_P, _P, ctypes.c_size_t],
@@ -351,6 +353,22 @@ def flbm_get_compact_pull(ctx, n_pad: int, tiles: int):
     _check(load_library().flbm_get_compact_pull(ctx, codes16.ctypes.data, codes8.ctypes.data, tail.ctypes.data,
                                                 hdr.ctypes.data), "flbm_get_compact_pull", ctx)
     return codes16, codes8, tail, hdr
+
+
+def flbm_pull_run_info(ctx):
+    """(8-bit tiles with run codes, their waves listing more than 256 codes)."""
+    t, w = ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().flbm_pull_run_info(ctx, ctypes.byref(t), ctypes.byref(w)), "flbm_pull_run_info", ctx)
+    return int(t.value), int(w.value)
+
+
+def flbm_get_pull_runs(ctx, n_pad: int):
+    """Host copy of the run codes: uint32 [n_pad][2] (mask, list bytes
+    4l..4l+3) and uint32 [n_pad] (list bytes 256+4l..256+4l+3)."""
+    runs = np.empty((n_pad, 2), np.uint32)
+    runs_hi = np.empty(n_pad, np.uint32)
+    _check(load_library().flbm_get_pull_runs(ctx, runs.ctypes.data, runs_hi.ctypes.data), "flbm_get_pull_runs", ctx)
+    return runs, runs_hi
 
 
 def flbm_state_bytes(ctx) -> int:
@@ -736,6 +754,10 @@ class Lattice:
     def pull_format(self):
         """(format, tiles with 8-bit codes, tiles with 16-bit codes, tiles)."""
         return flbm_pull_format_info(self.ctx)
+
+    def pull_runs(self):
+        """(8-bit tiles with run codes, their waves listing more than 256 codes)."""
+        return flbm_pull_run_info(self.ctx)
 
     def compact_pull(self):
         _, _, _, tiles = flbm_pull_format_info(self.ctx)

@@ -227,7 +227,7 @@ def test_compact_pull_table_decodes_to_the_definition(z_mode, px, py, fmt):
     mask[0, 0, 0] = 0
     ctx = fluxlbm.flbm_create(mask, _params(mask, periodic_x=px, periodic_y=py, z_mode=z_mode))
     try:
-        assert fluxlbm.flbm_pull_format_info(ctx)[0] == fluxlbm.FLBM_PULL_COMPACT  # the default
+        assert fluxlbm.flbm_pull_format_info(ctx)[0] == fluxlbm.FLBM_PULL_RUN  # the default
         fluxlbm.flbm_set_pull_format(ctx, fmt)
         n, npad, info, got, form, (_, _, _, hdr) = _compact(ctx)
         assert info[0] == fmt and info[3] == npad // 512
@@ -235,7 +235,7 @@ def test_compact_pull_table_decodes_to_the_definition(z_mode, px, py, fmt):
         if fmt == fluxlbm.FLBM_PULL_HALF:
             assert info[1] == 0
         assert np.array_equal(got, _brute_pull(mask, px, py, z_mode, npad))
-        assert not hdr[:, 19].any()
+        assert set(np.unique(hdr[:, 19])) <= {0, 1} and not hdr[hdr[:, 18] != 2, 19].any()
     finally:
         fluxlbm.flbm_destroy(ctx)
 
@@ -261,6 +261,7 @@ def test_compact_pull_table_falls_back_per_tile():
         assert not c16.reshape(9, tiles, 512)[:, t_form != 1].any()
         assert not c8.reshape(4, tiles, 512)[:, t_form != 2].any()
         assert not tail.reshape(tiles, 512)[t_form != 2].any()
+        assert not hdr[t_form != 2, 19].any()
         # an int32 tile really spans more than the 16-bit limit in some direction
         t = int(np.flatnonzero(t_form == 0)[0])
         rows = nbr[:, t * 512:min(n, (t + 1) * 512)]
@@ -281,14 +282,80 @@ def test_compact_pull_table_falls_back_per_tile():
         fluxlbm.flbm_destroy(ctx)
 
 
+def _byte_codes(codes8, tail, s, q):
+    if q <= 16:
+        return (codes8[(q - 1) // 4, s].astype(np.int64) >> (8 * ((q - 1) % 4))) & 0xFF
+    return (tail[s].astype(np.int64) >> (8 * (q - 17))) & 0xFF
+
+
+@pytest.mark.parametrize("case", ["pack", "random"])
+def test_run_codes_decode_to_the_byte_codes(case):
+    """Run codes (pull_format.h): per wave of 64 sites, the mask of the
+    directions whose byte code changes at each site and the list of the
+    changed codes. Decoded here with a running count per direction (not the
+    lane arithmetic of the kernel), they give every 8-bit code of every tile
+    that carries them; the tiles without them are exactly the 8-bit tiles
+    with a wave that would list more than 512 codes; the wide flag marks
+    exactly the waves listing more than 256."""
+    if case == "pack":
+        mask, _, _ = inputs.sphere_pack(48, 0.35, seed=7, reservoir_layers=4)
+    else:
+        mask = inputs.random_mask((20, 40, 40), 0.5, 3)
+    ctx = fluxlbm.flbm_create(mask, _params(mask))
+    try:
+        n, npad, info, _, form, (_, codes8, tail, hdr) = _compact(ctx)
+        runs, runs_hi = fluxlbm.flbm_get_pull_runs(ctx, npad)
+        n_runs, n_wide = fluxlbm.flbm_pull_run_info(ctx)
+        tiles = info[3]
+        flag = hdr[:, 19]
+        assert set(np.unique(flag)) <= {0, 1} and not flag[hdr[:, 18] != 2].any() and flag.sum() == n_runs
+        wide_seen = 0
+        for t in range(tiles):
+            if hdr[t, 18] != 2:
+                assert not runs[t * 512:(t + 1) * 512].any() and not runs_hi[t * 512:(t + 1) * 512].any()
+                continue
+            longest = 0
+            for w in range(8):
+                s = np.arange(t * 512 + 64 * w, t * 512 + 64 * w + 64)
+                listed = [np.r_[True, _byte_codes(codes8, tail, s, q)[1:] != _byte_codes(codes8, tail, s, q)[:-1]]
+                          for q in range(1, 19)]
+                e_total = int(sum(x.sum() for x in listed))
+                longest = max(longest, e_total)
+                if not flag[t]:
+                    continue
+                m = runs[s, 0]
+                wide = (m >> 31) & 1
+                assert (wide == (e_total > 256)).all()
+                wide_seen += int(e_total > 256)
+                lst = np.concatenate([np.ascontiguousarray(runs[s, 1]).view(np.uint8),
+                                      np.ascontiguousarray(runs_hi[s]).view(np.uint8)]).astype(np.int64)
+                off = 0
+                for q in range(1, 19):
+                    e = ((m >> (q - 1)) & 1).astype(bool)
+                    assert np.array_equal(e, listed[q - 1])
+                    got = lst[off + np.cumsum(e) - 1]
+                    off += int(e.sum())
+                    assert np.array_equal(got, _byte_codes(codes8, tail, s, q))
+                assert not (m & 0x7FFC0000).any()
+            assert (longest <= 512) == bool(flag[t])
+        assert wide_seen == n_wide
+        if case == "random":
+            assert 0 < n_runs < info[1] and n_wide > 0   # both kinds of 8-bit tile
+        else:
+            assert n_runs == info[1]
+    finally:
+        fluxlbm.flbm_destroy(ctx)
+
+
 def test_colour_model_reads_the_compact_pull_table():
     mask = inputs.random_mask((6, 8, 8), 0.2, 5)
     mask[0] = 0
     ctx = fluxlbm.flbm_create(mask, _params(mask, model=fluxlbm.FLBM_COLOUR))
     try:
         fmt, t8, t16, tiles = fluxlbm.flbm_pull_format_info(ctx)
-        assert fmt == fluxlbm.FLBM_PULL_COMPACT and t8 + t16 <= tiles and tiles >= 1
-        for fmt in (fluxlbm.FLBM_PULL_HALF, fluxlbm.FLBM_PULL_INT32, fluxlbm.FLBM_PULL_COMPACT):
+        assert fmt == fluxlbm.FLBM_PULL_RUN and t8 + t16 <= tiles and tiles >= 1
+        for fmt in (fluxlbm.FLBM_PULL_HALF, fluxlbm.FLBM_PULL_INT32, fluxlbm.FLBM_PULL_COMPACT,
+                    fluxlbm.FLBM_PULL_RUN):
             fluxlbm.flbm_set_pull_format(ctx, fmt)
             assert fluxlbm.flbm_pull_format_info(ctx)[0] == fmt
     finally:
@@ -304,7 +371,7 @@ def test_no_buffer_path_has_no_compact_pull_table(monkeypatch):
     ctx = fluxlbm.flbm_create(mask, _params(mask, model=fluxlbm.FLBM_COLOUR))
     try:
         assert fluxlbm.flbm_pull_format_info(ctx)[:3] == (fluxlbm.FLBM_PULL_INT32, 0, 0)
-        for fmt in (fluxlbm.FLBM_PULL_HALF, fluxlbm.FLBM_PULL_COMPACT):
+        for fmt in (fluxlbm.FLBM_PULL_HALF, fluxlbm.FLBM_PULL_COMPACT, fluxlbm.FLBM_PULL_RUN):
             with pytest.raises(fluxlbm.FlbmError) as e:
                 fluxlbm.flbm_set_pull_format(ctx, fmt)
             assert e.value.status == fluxlbm.FLBM_ESTATE

@@ -144,7 +144,8 @@ def test_autotune_picks_and_caches_a_schedule(tmp_path):
     # the key holds the model and the pull-table formats: with the int32
     # table the cached compact-table choice is not reused, a new one is added
     tag, _, prec, model, formats = open(cache).read().split()[:5]
-    assert tag == "v2" and prec == "1" and model == "0" and formats == "4"
+    default = {fluxlbm.FLBM_PULL_COMPACT: "4", fluxlbm.FLBM_PULL_RUN: "8"}[batched[0][1].pull_format()[0]]
+    assert tag == "v2" and prec == "1" and model == "0" and formats == default
     for _, l in batched:
         l.set_pull_format(fluxlbm.FLBM_PULL_INT32)
     b.autotune(cache, trial_steps=2)

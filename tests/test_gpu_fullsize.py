@@ -25,7 +25,7 @@ def test_bench_workload_one_step_against_oracle(precision, tol):
                     periodic_x=kw["periodic_x"], periodic_y=kw["periodic_y"])
     try:
         fmt, t8, t16, tiles = lat.pull_format()
-        assert fmt == fluxlbm.FLBM_PULL_COMPACT and t8 > 0.8 * tiles
+        assert fmt == fluxlbm.FLBM_PULL_RUN and t8 > 0.8 * tiles and lat.pull_runs()[0] > 0.8 * t8
         load_same_state(lat, orc, mask, 77, amp=0.02)
         lat.step(1)
         h_orc = orc.step(1)
@@ -50,11 +50,12 @@ def test_largest_workload_properties():
     lattice of the benchmarks): too large for the dense oracle, so the
     properties that hold at any size -- the inlet flux equals its target at
     every step, the state stays finite and subsonic, and the compact table
-    addresses the same slots as the int32 one (one step each way, bitwise)."""
+    addresses the same slots as the int32 one (16 steps each way, bitwise;
+    the run codes as well)."""
     mask, kw, _ = bench.make_workload(bench.CONFIGS["pack512"])
     print(f"largest: mask {mask.shape}", flush=True)
     outs = []
-    for fmt in (fluxlbm.FLBM_PULL_COMPACT, fluxlbm.FLBM_PULL_INT32):
+    for fmt in (fluxlbm.FLBM_PULL_RUN, fluxlbm.FLBM_PULL_INT32):
         lat = fluxlbm.Lattice(mask, watchdog_every=8, **kw)
         try:
             lat.set_pull_format(fmt)

@@ -1,9 +1,12 @@
 """The compact pull tables address the same slots as the int32 table, so a
 lattice stepped with any of them must hold bitwise equal states and
 histories: for every storage precision, BGK, MRT and the two-fluid colour
-model (both of its passes read the table), with the default forms, with a mix of 8-bit, 16-bit and int32 tiles (small code limits, and
-a lattice whose wide reservoir planes overflow the 16-bit codes at a
-y-wrap), and inside a batch that mixes the formats."""
+model (both of its passes read the table), with the default forms, with a
+mix of 8-bit, 16-bit and int32 tiles (small code limits, and a lattice whose
+wide reservoir planes overflow the 16-bit codes at a y-wrap), with the 8-bit
+codes read as run codes (waves whose list of codes needs a second word, and
+8-bit tiles too irregular for run codes beside them), and inside a batch
+that mixes the formats."""
 import numpy as np
 import pytest
 
@@ -31,7 +34,7 @@ def _run(mask, fmt, limits, precision, model, steps, q=0.3, tau=0.8):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 @pytest.mark.parametrize("model", ["bgk", "mrt"])
-@pytest.mark.parametrize("fmt,limits", [(2, (0, 0)), (2, (600, 100)), (1, (0, 0))])
+@pytest.mark.parametrize("fmt,limits", [(3, (0, 0)), (3, (600, 100)), (2, (0, 0)), (2, (600, 100)), (1, (0, 0))])
 def test_compact_equals_int32_bitwise(precision, model, fmt, limits):
     mask = _pack(40, 11)
     print(f"pull format: {precision} {model} format {fmt} limits {limits}", flush=True)
@@ -45,13 +48,33 @@ def test_compact_equals_int32_bitwise(precision, model, fmt, limits):
     assert np.array_equal(h0[:, :3], h1[:, :3])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
+def test_run_codes_beside_irregular_byte_tiles(precision):
+    # independent random solids (half the voxels): most waves change codes at
+    # nearly every site, so most 8-bit tiles are too irregular for run codes;
+    # the one tile that has them needs the second word in every wave
+    mask = inputs.random_mask((20, 40, 40), 0.5, 3)
+    lat = fluxlbm.Lattice(mask, precision="fp32", tau=0.8, q_target=0.1)
+    try:
+        _, t8, t16, _ = lat.pull_format()
+        runs, wide = lat.pull_runs()
+    finally:
+        lat.close()
+    print(f"run codes: {precision}; {t8} 8-bit tiles, {runs} with run codes ({wide} wide waves)", flush=True)
+    assert 0 < runs < t8 and wide > 0 and t16 > 0
+    f0, h0, _ = _run(mask, fluxlbm.FLBM_PULL_INT32, (0, 0), precision, "bgk", 40, q=0.1)
+    f1, h1, _ = _run(mask, fluxlbm.FLBM_PULL_RUN, (0, 0), precision, "bgk", 40, q=0.1)
+    assert np.array_equal(f0, f1)
+    assert np.array_equal(h0[:, :3], h1[:, :3])
+
+
 def test_wide_reservoir_planes_fall_back():
     # 300 x 300 planes: a fluid reservoir plane holds 90,000 sites, so the
     # tiles that hold a y-wrap have sources farther apart than 16 bits
     mask = np.zeros((10, 300, 300), np.uint8)
     mask[3:7] = inputs.random_mask((4, 300, 300), 0.3, 21)
     f0, h0, _ = _run(mask, fluxlbm.FLBM_PULL_INT32, (0, 0), "fp32", "bgk", 24, q=2.0)
-    f1, h1, info = _run(mask, fluxlbm.FLBM_PULL_COMPACT, (0, 0), "fp32", "bgk", 24, q=2.0)
+    f1, h1, info = _run(mask, fluxlbm.FLBM_PULL_RUN, (0, 0), "fp32", "bgk", 24, q=2.0)
     print(f"wide planes: {info[1]} byte, {info[2]} 16-bit of {info[3]} tiles", flush=True)
     assert info[1] + info[2] < info[3]
     assert np.array_equal(f0, f1)
@@ -59,9 +82,9 @@ def test_wide_reservoir_planes_fall_back():
 
 
 def test_batch_mixing_formats_equals_singles():
-    masks = [_pack(24, 31), _pack(32, 32), _pack(20, 33), _pack(28, 34)]
-    fmts = [(fluxlbm.FLBM_PULL_COMPACT, 0, 0), (fluxlbm.FLBM_PULL_INT32, 0, 0),
-            (fluxlbm.FLBM_PULL_COMPACT, 800, 100), (fluxlbm.FLBM_PULL_HALF, 0, 0)]
+    masks = [_pack(24, 31), _pack(32, 32), _pack(20, 33), _pack(28, 34), _pack(24, 35)]
+    fmts = [(fluxlbm.FLBM_PULL_RUN, 0, 0), (fluxlbm.FLBM_PULL_INT32, 0, 0),
+            (fluxlbm.FLBM_PULL_RUN, 800, 100), (fluxlbm.FLBM_PULL_HALF, 0, 0), (fluxlbm.FLBM_PULL_COMPACT, 0, 0)]
 
     def make():
         out = []
@@ -91,7 +114,7 @@ def test_batch_mixing_formats_equals_singles():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
-@pytest.mark.parametrize("fmt,limits", [(2, (0, 0)), (2, (600, 100)), (1, (0, 0))])
+@pytest.mark.parametrize("fmt,limits", [(3, (0, 0)), (2, (0, 0)), (2, (600, 100)), (1, (0, 0))])
 def test_colour_compact_equals_int32_bitwise(precision, fmt, limits):
     """Colour model, flux set-up with a non-wetting inlet reservoir: the phase
     pass (directions 1..6) and the colour step (all 18, and the neighbours'
