@@ -538,7 +538,7 @@ __global__ __launch_bounds__(TILE / PHASE_V) void k_phase_buf(PhaseArgs p, StepA
                         ? (uint32_t)buf_load_raw<4, SC_IDX_AUX>(rn, s[v] * 4u, (uint32_t)(q - 1) * npad * 4u)
                         : pull_code<FORM>(w[v], tail[v], q);
                 int kind;
-                const uint32_t base = FORM == PULL_TILE_INT32 ? 0u : (uint32_t)hdr[q - 1];
+                const uint32_t base = FORM == PULL_TILE_INT32 ? 0u : hdr_entry(hdr, q - 1);
                 const uint32_t idx = decode_pull<FORM>(code, base, pos[v], (uint32_t)d3q19::opp(q) * npad + s[v],
                                                        sent, (uint32_t)q, npad, kind);
                 // the colour array has 7 rows: an unknown reads the site's own
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
                                   : FORM == FORM_RUN ? run_code(rw, q, off)
                                                      : pull_code<CODES>(w, tail, q);
             int kind;
-            const uint32_t base = FORM == PULL_TILE_INT32 ? 0u : (uint32_t)hdr[q - 1];
+            const uint32_t base = FORM == PULL_TILE_INT32 ? 0u : hdr_entry(hdr, q - 1);
             const uint32_t idx = decode_pull<CODES>(code, base, pos, (uint32_t)d3q19::opp(q) * npad + s, sent,
                                                     (uint32_t)q, npad, kind);
             g[q] = Codec<T>::dec(__builtin_bit_cast(T, buf_load_raw<sizeof(T)>(rf, idx * fsz, 0u)), q);

@@ -737,6 +737,16 @@ __device__ __forceinline__ void rescale_pops(R (&g)[19])
     }
 }
 
+// Entry i of a tile header, read as the uniform value it is. The read is a
+// convergent operation, so the compiler cannot sink it into the branch of
+// the one code kind that uses it: sunk there, in the batched kernels (whose
+// header pointer comes from memory) it became a vector load and a wait for
+// every load in flight, once per direction, a quarter of the step.
+__device__ __forceinline__ uint32_t hdr_entry(const int32_t *hdr, int i)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane(hdr[i]);
+}
+
 // The byte codes of V consecutive sites from s0 (see pull_format.h):
 // directions 1..16 in four words per site (w[k] holds 4k+1..4k+4), 17 and
 // 18 in a 16-bit tail.
@@ -794,7 +804,7 @@ __device__ __forceinline__ uint32_t run_code(const RunWave &r, int q, uint32_t &
 // The work of one tile (SC_BLOCK threads), shared by the single-lattice
 // kernel (one tile per block) and the batched kernel (a work list of tiles
 // of many lattices per block).
-template <typename T, bool OBS, bool BUF, bool MRT>
+template <typename T, bool OBS, bool BUF, bool MRT, bool RUNS = true>
 __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__restrict__ fin,
                                                     T *__restrict__ fout, const int32_t *__restrict__ nbr,
                                                     const StepArgs &a, const int rd)
@@ -831,7 +841,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         // lane count and a cross-lane read per direction) made it 3 % slower,
         // while the 10 bytes per site they save take 4 % off the FP32 step,
         // which waits on bandwidth
-        const bool runs_on = V == 1 && !SPEC && a.pull_runs != nullptr;
+        const bool runs_on = RUNS && V == 1 && !SPEC && a.pull_runs != nullptr;
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.pull_runs, a.runs_bytes);
         uint32_t w[4][V];
         uint16_t tl[V];
@@ -850,7 +860,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         const uint32_t p0 = (uint32_t)(s0 - (int64_t)tile * TILE);
         // byte code c of direction q: flat index = base + position + code
         auto pull_byte = [&](int q, int v, uint32_t c) {
-            const uint32_t base = (uint32_t)hdr[q - 1];
+            const uint32_t base = hdr_entry(hdr, q - 1);
             const uint32_t bb = (uint32_t)d3q19::opp(q) * (uint32_t)npad + (uint32_t)s0;
             const uint32_t idx = c <= PULL_MAX_BYTE ? base + p0 + (uint32_t)v + c
                                  : (c == PULL_BYTE_BOUNCE ? bb + (uint32_t)v : sent);
@@ -886,7 +896,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     const int q = 2 * k + 1 + half;
-                    const uint32_t base = (uint32_t)hdr[q - 1];
+                    const uint32_t base = hdr_entry(hdr, q - 1);
                     const uint32_t bb = (uint32_t)d3q19::opp(q) * (uint32_t)npad + (uint32_t)s0;
 #pragma unroll
                     for (int v = 0; v < V; ++v) {
@@ -1025,6 +1035,11 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
     stream_collide_tile<T, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a, a.rd);
 }
 
+// The batched kernels read the byte codes: with run codes their step took
+// 2.97 instead of 2.14 ms on 64 packs of 64^3 to 192^3 (the single-lattice
+// step gains from them).
+constexpr bool BATCH_RUNS = false;
+
 // Batched step: many lattices in one launch. Each lattice keeps its own
 // buffers, pull table, state and partials (its StepArgs); a work list of
 // (lattice, tile range) items is walked by a persistent grid, block b taking
@@ -1053,7 +1068,7 @@ __global__ __launch_bounds__(SC_BLOCK) void k_batch_step(const BatchSample *__re
         const T *fin = (const T *)(parity ? S->f1 : S->f0);
         T *fout = (T *)(parity ? S->f0 : S->f1);
         for (int t = it.t0; t < it.t1; ++t) {
-            stream_collide_tile<T, OBS, BUF, MRT>(t, fin, fout, S->nbr, a, rd);
+            stream_collide_tile<T, OBS, BUF, MRT, BATCH_RUNS>(t, fin, fout, S->nbr, a, rd);
             __syncthreads();  // the tile's LDS reductions are reused by the next tile
         }
     }
@@ -1073,7 +1088,7 @@ __device__ __forceinline__ void batch_tile_body(const BatchSample *__restrict__ 
     const StepArgs a = S->a;
     const T *fin = (const T *)(parity ? S->f1 : S->f0);
     T *fout = (T *)(parity ? S->f0 : S->f1);
-    stream_collide_tile<T, OBS, BUF, MRT>(it.t0, fin, fout, S->nbr, a, a.rd ^ parity);
+    stream_collide_tile<T, OBS, BUF, MRT, BATCH_RUNS>(it.t0, fin, fout, S->nbr, a, a.rd ^ parity);
 }
 
 template <typename T, bool OBS, bool BUF, bool MRT>
