@@ -255,7 +255,7 @@ def run_batch(args, cfg):
     e1.record(stream)
     torch.cuda.synchronize()
     ms_seq = e0.elapsed_time(e1) / k_seq
-    bpl = bytes_per_lup(cfg["precision"], "bgk", *share[:2])  # the batched kernels read the byte codes
+    bpl = bytes_per_lup(cfg["precision"], "bgk", *share)
     bpl_s = bytes_per_lup_survey(cfg["precision"], "bgk")
     achieved = n_total * bpl / (ms_kernel * 1e-3) / 1e9
     achieved_s = n_total * bpl_s / (ms_kernel * 1e-3) / 1e9

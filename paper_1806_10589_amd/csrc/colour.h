@@ -503,7 +503,7 @@ __global__ __launch_bounds__(TILE / PHASE_V) void k_phase_buf(PhaseArgs p, StepA
     const __amdgpu_buffer_rsrc_t rab = make_rsrc(p.abin, 7u * npad * (uint32_t)PB);
     const uint32_t esz = (uint32_t)sizeof(C);
     const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
-    const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
+    const int form = hdr ? (int)hdr_entry(hdr, PULL_HDR_FORM) : PULL_TILE_INT32;
     const uint32_t sent = 19u * npad;
     uint32_t pos[V], s[V];
 #pragma unroll
@@ -655,7 +655,7 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
     R gx = 0, gy = 0, gz = 0;
     const R phs = (R)c.phi_solid;
     const int32_t *hdr = a.pull_hdr ? a.pull_hdr + (int64_t)tile * PULL_HDR : nullptr;
-    const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
+    const int form = hdr ? (int)hdr_entry(hdr, PULL_HDR_FORM) : PULL_TILE_INT32;
     const uint32_t sent = 19u * npad, pos = threadIdx.x;
     // FORM_RUN: a tile of 8-bit codes read as run codes (see pull_format.h)
     constexpr int FORM_RUN = 3;
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
     // run codes where the table has them, except in FP16 storage (the same
     // rule and reason as the single-fluid step: 2 % off the FP32 colour
     // step, 3 % onto the FP16 one)
-    if (form == PULL_TILE_BYTE && !std::is_same<T, _Float16>::value && a.pull_runs && hdr[PULL_HDR_RUNS])
+    if (form == PULL_TILE_BYTE && !std::is_same<T, _Float16>::value && a.pull_runs && hdr_entry(hdr, PULL_HDR_RUNS))
         gather(std::integral_constant<int, FORM_RUN>{});
     else if (form == PULL_TILE_BYTE)
         gather(std::integral_constant<int, PULL_TILE_BYTE>{});

@@ -737,14 +737,17 @@ __device__ __forceinline__ void rescale_pops(R (&g)[19])
     }
 }
 
-// Entry i of a tile header, read as the uniform value it is. The read is a
-// convergent operation, so the compiler cannot sink it into the branch of
-// the one code kind that uses it: sunk there, in the batched kernels (whose
-// header pointer comes from memory) it became a vector load and a wait for
-// every load in flight, once per direction, a quarter of the step.
+// Entry i of a tile header, read as the uniform value it is: through the
+// constant address space (the header is never written while a step runs),
+// so that it is a scalar load even where the pointer itself was read from
+// memory (the batched kernels), and through readfirstlane, a convergent
+// operation the compiler cannot sink into the branch of the one code kind
+// that uses it. As a vector load sunk into that branch, followed by a wait
+// for every load in flight, it cost the batched step a quarter of its time.
+typedef const int32_t __attribute__((address_space(4))) *ConstI32;
 __device__ __forceinline__ uint32_t hdr_entry(const int32_t *hdr, int i)
 {
-    return (uint32_t)__builtin_amdgcn_readfirstlane(hdr[i]);
+    return (uint32_t)__builtin_amdgcn_readfirstlane(((ConstI32)hdr)[i]);
 }
 
 // The byte codes of V consecutive sites from s0 (see pull_format.h):
@@ -804,7 +807,7 @@ __device__ __forceinline__ uint32_t run_code(const RunWave &r, int q, uint32_t &
 // The work of one tile (SC_BLOCK threads), shared by the single-lattice
 // kernel (one tile per block) and the batched kernel (a work list of tiles
 // of many lattices per block).
-template <typename T, bool OBS, bool BUF, bool MRT, bool RUNS = true>
+template <typename T, bool OBS, bool BUF, bool MRT>
 __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__restrict__ fin,
                                                     T *__restrict__ fout, const int32_t *__restrict__ nbr,
                                                     const StepArgs &a, const int rd)
@@ -841,7 +844,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         // lane count and a cross-lane read per direction) made it 3 % slower,
         // while the 10 bytes per site they save take 4 % off the FP32 step,
         // which waits on bandwidth
-        const bool runs_on = RUNS && V == 1 && !SPEC && a.pull_runs != nullptr;
+        const bool runs_on = V == 1 && !SPEC && a.pull_runs != nullptr;
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.pull_runs, a.runs_bytes);
         uint32_t w[4][V];
         uint16_t tl[V];
@@ -854,7 +857,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
                     load_byte_codes<V>(make_rsrc(a.pull_bytes, a.bytes_bytes), (uint32_t)s0, (uint32_t)npad, w, tl);
             }
         }
-        const int form = hdr ? hdr[PULL_HDR_FORM] : PULL_TILE_INT32;
+        const int form = hdr ? (int)hdr_entry(hdr, PULL_HDR_FORM) : PULL_TILE_INT32;
         const uint32_t sent = 19u * (uint32_t)npad;
         // position of each of this thread's sites in the tile
         const uint32_t p0 = (uint32_t)(s0 - (int64_t)tile * TILE);
@@ -868,7 +871,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
             buf_load_v<1, T, T>(rf, idx * (uint32_t)sizeof(T), 0u, r);
             g[v][q] = load_pop<T, SCALED>(r[0], q);
         };
-        if (form == PULL_TILE_BYTE && runs_on && hdr[PULL_HDR_RUNS]) {
+        if (form == PULL_TILE_BYTE && runs_on && hdr_entry(hdr, PULL_HDR_RUNS)) {
             if constexpr (!SPEC) rw = load_runs(rr, (uint32_t)s0);
             load_runs_wide(rw, rr, (uint32_t)s0, (uint32_t)npad);
             uint32_t off = 0;
@@ -1035,11 +1038,6 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
     stream_collide_tile<T, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a, a.rd);
 }
 
-// The batched kernels read the byte codes: with run codes their step took
-// 2.97 instead of 2.14 ms on 64 packs of 64^3 to 192^3 (the single-lattice
-// step gains from them).
-constexpr bool BATCH_RUNS = false;
-
 // Batched step: many lattices in one launch. Each lattice keeps its own
 // buffers, pull table, state and partials (its StepArgs); a work list of
 // (lattice, tile range) items is walked by a persistent grid, block b taking
@@ -1068,7 +1066,7 @@ __global__ __launch_bounds__(SC_BLOCK) void k_batch_step(const BatchSample *__re
         const T *fin = (const T *)(parity ? S->f1 : S->f0);
         T *fout = (T *)(parity ? S->f0 : S->f1);
         for (int t = it.t0; t < it.t1; ++t) {
-            stream_collide_tile<T, OBS, BUF, MRT, BATCH_RUNS>(t, fin, fout, S->nbr, a, rd);
+            stream_collide_tile<T, OBS, BUF, MRT>(t, fin, fout, S->nbr, a, rd);
             __syncthreads();  // the tile's LDS reductions are reused by the next tile
         }
     }
@@ -1088,7 +1086,7 @@ __device__ __forceinline__ void batch_tile_body(const BatchSample *__restrict__ 
     const StepArgs a = S->a;
     const T *fin = (const T *)(parity ? S->f1 : S->f0);
     T *fout = (T *)(parity ? S->f0 : S->f1);
-    stream_collide_tile<T, OBS, BUF, MRT, BATCH_RUNS>(it.t0, fin, fout, S->nbr, a, a.rd ^ parity);
+    stream_collide_tile<T, OBS, BUF, MRT>(it.t0, fin, fout, S->nbr, a, a.rd ^ parity);
 }
 
 template <typename T, bool OBS, bool BUF, bool MRT>

@@ -181,6 +181,35 @@ def test_colour_checkpoint_resume_is_bitwise():
     assert np.array_equal(f1, f2) and np.array_equal(A1, A2) and np.array_equal(B1, B2)
 
 
+@pytest.mark.parametrize("fmt", [fluxlbm.FLBM_PULL_RUN, fluxlbm.FLBM_PULL_COMPACT])
+def test_colour_fp64_repeats_bitwise(fmt):
+    """Two identical FP64 colour runs agree bit for bit over 100 steps. The
+    FP64 colour step once stored its (A, B) pairs with 16-byte stores whose
+    data registers the next instruction overwrote, which on gfx950 left the
+    next direction's advection factor in A in four lanes of every sixteen,
+    differently from run to run (the pairs are now stored in 8-byte halves)."""
+    mask, _, _ = inputs.sphere_pack(48, 0.30, seed=3, reservoir_layers=6)
+    sites = inputs.pore_sites(mask)
+    z = sites // (mask.shape[1] * mask.shape[2])
+    na = (z < 6).astype(float)
+
+    def run():
+        lat = fluxlbm.Lattice(mask, precision="fp64", model="colour", tau=1.0, q_target=0.01, alpha=0.0157,
+                              beta=0.7, phi_solid=-0.7071, periodic_x=True, periodic_y=True, watchdog_every=50)
+        try:
+            lat.set_pull_format(fmt)
+            lat.init_colour(na, 1.0 - na)
+            lat.step(100)
+            A, B = lat.read_colour()
+            return lat.read_distributions(), A, B
+        finally:
+            lat.close()
+
+    f0, A0, B0 = run()
+    f1, A1, B1 = run()
+    assert np.array_equal(f0, f1) and np.array_equal(A0, A1) and np.array_equal(B0, B1)
+
+
 @pytest.fixture(scope="module")
 def crop64():
     """64^3 crop of the 384^3 sphere pack (seed 3, porosity 0.30) with the
