@@ -601,6 +601,11 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_copy:
         out["copy_gbs"] = round(copy_bandwidth(torch), 1)
+        # the same fractions against the stream copy measured in this run
+        out["roofline"]["frac_copy"] = round(roofline["achieved"] / out["copy_gbs"], 4)
+        out["roofline"]["frac_survey_copy"] = round(roofline["achieved_survey"] / out["copy_gbs"], 4)
+        if roofline.get("traffic_gbs"):
+            out["roofline"]["traffic_frac_copy"] = round(roofline["traffic_gbs"] / out["copy_gbs"], 4)
     if args.config == "pack256" and not args.no_pack512:
         out["pack512"] = pack512_line(args)
     if not args.no_controller and args.config == "pack256":
