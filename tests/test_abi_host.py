@@ -183,6 +183,8 @@ def test_batch_and_network_argument_checks_without_a_device():
     assert lib.flbm_batch_set_schedule(None, None) == fluxlbm.FLBM_EINVAL
     assert lib.flbm_gemm_bf16(None, 1, 1, None, 1, 1, None, 1, 1, 1, 1, None) == fluxlbm.FLBM_EINVAL
     assert lib.flbm_set_controller(None, None, None) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_pull_run_info(None, None, None) == fluxlbm.FLBM_EINVAL
+    assert lib.flbm_get_pull_runs(None, None, None) == fluxlbm.FLBM_EINVAL
 
 
 _OPP = [0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17]
@@ -375,6 +377,10 @@ def test_no_buffer_path_has_no_compact_pull_table(monkeypatch):
             with pytest.raises(fluxlbm.FlbmError) as e:
                 fluxlbm.flbm_set_pull_format(ctx, fmt)
             assert e.value.status == fluxlbm.FLBM_ESTATE
+        assert fluxlbm.flbm_pull_run_info(ctx) == (0, 0)
+        with pytest.raises(fluxlbm.FlbmError) as e:
+            fluxlbm.flbm_get_pull_runs(ctx, 1024)
+        assert e.value.status == fluxlbm.FLBM_ESTATE
     finally:
         fluxlbm.flbm_destroy(ctx)
 
