@@ -100,6 +100,28 @@ def test_all_solid_inlet_is_enoinlet():
     fluxlbm.flbm_destroy(ctx)
 
 
+def test_mask_without_pores_is_einval():
+    mask = np.ones((6, 4, 4), np.uint8)
+    for z_mode in (fluxlbm.FLBM_Z_FLUX, fluxlbm.FLBM_Z_PERIODIC):
+        with pytest.raises(fluxlbm.FlbmError) as e:
+            fluxlbm.flbm_create(mask, _params(mask, z_mode=z_mode))
+        assert e.value.status == fluxlbm.FLBM_EINVAL
+
+
+def test_lattice_beyond_32_bit_indices_is_eindex():
+    # The largest flat index is 19 n_pad plus the 64-element pad behind the
+    # sentinel; n_pad (a multiple of 1024) may reach 113,025,024. One pore
+    # site more pads to 113,026,048 and is refused, before any per-site
+    # allocation.
+    mask = np.zeros((484, 484, 484), np.uint8)
+    flat = mask.reshape(-1)
+    plane = 484 * 484
+    flat[plane:plane + mask.size - 113_025_025] = 1
+    with pytest.raises(fluxlbm.FlbmError) as e:
+        fluxlbm.flbm_create(mask, _params(mask))
+    assert e.value.status == fluxlbm.FLBM_EINDEX
+
+
 def _brute_pull(mask, px, py, z_mode, npad):
     """Expected pull index of (q, s) from the definition of streaming."""
     cx = [0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0]
