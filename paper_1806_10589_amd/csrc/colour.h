@@ -139,6 +139,8 @@ __global__ __launch_bounds__(BLOCK) void k_phase(PhaseArgs p)
         const DevState *st = p.st;
         if (s < p.a_in) {
             // pure non-wetting injection: A_5 = w_5 (1 + 9/2 u_z), B_5 = 0
+            // (s_carry[rd] holds the inlet sum: the colour model ends every
+            // step in a launch of its own)
             const double drho_in = inlet_drho(st, p.rd, p.rho0, p.a_in);
             const double uz = inlet_velocity(g, drho_in, p.rho0);
             a[5] = (R)(d3q19::weight7(5) * (1.0 + 4.5 * uz));
@@ -194,6 +196,7 @@ __global__ __launch_bounds__(TILE, (sizeof(T) <= 4 && !OBS) ? 6 : 1) void k_colo
     const int64_t s = (int64_t)tile * TILE + threadIdx.x;
     const int64_t npad = a.npad;
     const C *phi = (const C *)c.phi;
+    const double drho_in = step_begin<TILE>(tile, a, a.rd);
 
     // pull f, and with the same indices the colour gradient: the neighbour
     // x + xi_q is the source of pull direction opp(q), so
@@ -214,13 +217,10 @@ __global__ __launch_bounds__(TILE, (sizeof(T) <= 4 && !OBS) ? 6 : 1) void k_colo
     }
 
     double uz_in = 0.0, uz_out = 0.0;
-    if (tile < a.nt_in && s < a.a_in) {
-        const double drho_in = inlet_drho(a.st, a.rd, a.rho0, a.a_in);
-        uz_in = inlet_condition(g, drho_in, a.rho0);
-    }
-    if (tile >= a.tout0 && s >= a.out0 && s < a.n) uz_out = outlet_condition(g, a.st->drho_out, a.rho0);
+    if (tile < a.nt_in && s < a.a_in) uz_in = inlet_condition(g, drho_in, a.rho0);
+    if (tile >= a.tout0 && s >= a.out0 && s < a.n) uz_out = outlet_condition(g, cst(a.st)->drho_out, a.rho0);
 
-    const R snu = (R)a.st->omega;
+    const R snu = (R)cst(a.st)->omega;
     const bool collide = snu != (R)0;
     R drho, ux, uy, uz;
     if (collide) {
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(TILE, (sizeof(T) <= 4 && !OBS) ? 6 : 1) void k_colo
         u2max = (float)(ux * ux + uy * uy + uz * uz);
         bad = !isfinite((double)drho + (double)ux + (double)uy + (double)uz + (double)na + (double)nb);
     }
-    step_epilogue<TILE, OBS, true>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, (double)na, (double)nb);
+    step_epilogue<TILE, OBS, true>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, a.rd, (double)na, (double)nb);
 }
 
 // ---------------------------------------------------------------- buffer path
@@ -576,6 +576,8 @@ __global__ __launch_bounds__(TILE / PHASE_V) void k_phase_buf(PhaseArgs p, StepA
             const C2 *abin = (const C2 *)p.abin;
             if (sv < p.a_in) {
                 // pure non-wetting injection: A_5 = w_5 (1 + 9/2 u_z), B_5 = 0
+                // (s_carry[rd] holds the inlet sum: the colour model ends
+                // every step in a launch of its own)
                 const double drho_in = inlet_drho(st, p.rd, p.rho0, p.a_in);
                 const double uz = inlet_velocity(g, drho_in, p.rho0);
                 av[v][5] = (R)(d3q19::weight7(5) * (1.0 + 4.5 * uz));
@@ -706,14 +708,13 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
         gather(std::integral_constant<int, PULL_TILE_INT32>{});
 
     double uz_in = 0.0, uz_out = 0.0;
-    if (tile < a.nt_in && (int64_t)s < a.a_in) {
-        const double drho_in = inlet_drho(a.st, a.rd, a.rho0, a.a_in);
-        uz_in = inlet_condition(g, drho_in, a.rho0);
-    }
+    // after the gathers are issued (as in the single-fluid step)
+    const double drho_in = step_begin<TILE>(tile, a, a.rd);
+    if (tile < a.nt_in && (int64_t)s < a.a_in) uz_in = inlet_condition(g, drho_in, a.rho0);
     if (tile >= a.tout0 && (int64_t)s >= a.out0 && (int64_t)s < a.n)
-        uz_out = outlet_condition(g, a.st->drho_out, a.rho0);
+        uz_out = outlet_condition(g, cst(a.st)->drho_out, a.rho0);
 
-    const R snu = (R)a.st->omega;
+    const R snu = (R)cst(a.st)->omega;
     const bool collide = snu != (R)0;
     R drho, ux, uy, uz;
     if (collide) {
@@ -747,7 +748,6 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
 
     // recolouring: full relaxation of A and B to
     //   w_q N_A [1 + 9/2 u.xi_q + beta N_B n.xi_q],  w_q N_B [1 + 9/2 u.xi_q - beta N_A n.xi_q]
-    typedef typename Pair<C>::type C2;
     constexpr int PB = 2 * sizeof(C);
     R na, nb;
     colour_densities<R, C>(c.nab, c.phi, s, npad, na, nb);
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
         u2max = (float)(ux * ux + uy * uy + uz * uz);
         bad = !isfinite((double)drho + (double)ux + (double)uy + (double)uz + (double)na + (double)nb);
     }
-    step_epilogue<TILE, OBS, true>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, (double)na, (double)nb);
+    step_epilogue<TILE, OBS, true>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, a.rd, (double)na, (double)nb);
 }
 
 // Phase field of a stored colour state (for readout): phi from the stored A, B.

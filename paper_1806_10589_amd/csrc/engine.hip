@@ -198,9 +198,10 @@ size_t carve(flbm_ctx *c, char *base)
     char *pcr = c->pull.tiles ? take(pull_runs_size(c)) : nullptr;
     char *st = take(sizeof(DevState));
     char *kp = take(PLANE_MAX_BLOCKS * sizeof(double));
-    char *bi = take((size_t)std::max(1, c->nt_in) * sizeof(double));
-    char *bo = take((size_t)std::max(1, c->tiles - c->tout0) * sizeof(double));
-    char *sp = take((size_t)std::max(1, c->nt01) * sizeof(double));
+    // boundary partials: two slots (the step that wrote buffer 0, 1) of one per tile
+    char *bi = take((size_t)2 * c->tiles * sizeof(double));
+    char *bo = take((size_t)2 * c->tiles * sizeof(double));
+    char *sp = take((size_t)2 * c->tiles * sizeof(double));
     char *kc = take((size_t)std::max<int64_t>(1, (int64_t)c->lat.kcoef.size()) * sizeof(uint64_t));
     char *om = take((size_t)c->obs_slots * sizeof(double));
     char *ou = take((size_t)c->obs_slots * sizeof(float));
@@ -285,6 +286,7 @@ StepArgs step_args(const flbm_ctx *c)
     a.st = c->st;
     a.bpart_in = c->bpart_in;
     a.bpart_out = c->bpart_out;
+    a.part_stride = c->tiles;
     a.obs_mass = c->obs_mass;
     a.obs_umax2 = c->obs_umax2;
     a.obs_bad = c->obs_bad;
@@ -381,21 +383,30 @@ void launch_colour_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
 // The fused kernel in its variants: with or without the watchdog partials;
 // buffer instructions (buffers below 4 GiB) or 64-bit addressing; BGK or
 // single-fluid MRT collision.
+template <typename T, bool OBS, bool BUF, bool MRT>
+void launch_sc(dim3 grid, hipStream_t s, const T *fin, T *fout, const int32_t *nbr, const StepArgs &a)
+{
+    if constexpr (std::is_same<T, _Float16>::value)
+        hipLaunchKernelGGL((k_stream_collide_h<OBS, BUF, MRT>), grid, dim3(SC_BLOCK), 0, s, fin, fout, nbr, a);
+    else
+        hipLaunchKernelGGL((k_stream_collide<T, OBS, BUF, MRT>), grid, dim3(SC_BLOCK), 0, s, fin, fout, nbr, a);
+}
+
 template <typename T, bool MRT>
 void launch_stream_collide_c(flbm_ctx *c, hipStream_t s, const T *fin, T *fout, bool obs, const StepArgs &a)
 {
     Range r(c->markers, "flbm stream-collide");
-    const dim3 grid(c->tiles), block(SC_BLOCK);
+    const dim3 grid(c->tiles);
     if (c->use_buf) {
         if (obs)
-            hipLaunchKernelGGL((k_stream_collide<T, true, true, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+            launch_sc<T, true, true, MRT>(grid, s, fin, fout, c->nbr, a);
         else
-            hipLaunchKernelGGL((k_stream_collide<T, false, true, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+            launch_sc<T, false, true, MRT>(grid, s, fin, fout, c->nbr, a);
     } else {
         if (obs)
-            hipLaunchKernelGGL((k_stream_collide<T, true, false, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+            launch_sc<T, true, false, MRT>(grid, s, fin, fout, c->nbr, a);
         else
-            hipLaunchKernelGGL((k_stream_collide<T, false, false, MRT>), grid, block, 0, s, fin, fout, c->nbr, a);
+            launch_sc<T, false, false, MRT>(grid, s, fin, fout, c->nbr, a);
     }
 }
 
@@ -420,21 +431,22 @@ void launch_finalize(flbm_ctx *c, hipStream_t s, int from)
     hipLaunchKernelGGL(k_step_finalize, dim3(1), dim3(FIN_BLOCK), 0, s, a);
 }
 
-// Enqueue one step from buffer `from` on stream s.
+// Enqueue one step from buffer `from` on stream s; fin: end it with
+// k_step_finalize (else the next step kernel ends it, see step_begin).
 template <typename T>
-void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs)
+void launch_step(flbm_ctx *c, hipStream_t s, int from, bool obs, bool fin)
 {
-    const T *fin = (const T *)c->f[from];
+    const T *fin_buf = (const T *)c->f[from];
     T *fout = (T *)c->f[from ^ 1];
-    launch_stream_collide<T>(c, s, fin, fout, obs);
-    launch_finalize(c, s, from);
+    launch_stream_collide<T>(c, s, fin_buf, fout, obs);
+    if (fin || obs) launch_finalize(c, s, from);
     if (obs) {
         Range r(c->markers, "flbm observables");
         hipLaunchKernelGGL(k_obs_finalize, dim3(1), dim3(OBS_BLOCK), 0, s, obs_args(c, 1, c->tiles));
     }
 }
 
-void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
+void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs, bool fin)
 {
     if (c->colour) {
         with_storage(c, [&](auto tag) { launch_colour_step<decltype(tag)>(c, s, from, obs); });
@@ -445,7 +457,7 @@ void launch_step_plain(flbm_ctx *c, hipStream_t s, int from, bool obs)
         }
         return;
     }
-    with_storage(c, [&](auto tag) { launch_step<decltype(tag)>(c, s, from, obs); });
+    with_storage(c, [&](auto tag) { launch_step<decltype(tag)>(c, s, from, obs, fin); });
 }
 
 // Learned inlet controller (one workgroup, launched after every step
@@ -596,9 +608,14 @@ void launch_controller(flbm_ctx *c, hipStream_t s, int rd_next)
     hipLaunchKernelGGL(k_controller, dim3(1), dim3(256), 0, s, a);
 }
 
-void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool obs)
+// One step of a run; last: the run's last step (it records the watchdog's
+// observables and ends in a launch of its own). Inside a run the next step
+// kernel ends each single-fluid step (step_begin), which saves a launch per
+// step; the controller reads every step's outlet flux from its end, so with
+// it each step ends in its own launch, as in the colour model.
+void launch_step_any(flbm_ctx *c, hipStream_t s, int from, bool last)
 {
-    launch_step_plain(c, s, from, obs);
+    launch_step_plain(c, s, from, last, last || c->ctrl_on);
     if (c->ctrl_on) {
         Range r(c->markers, "flbm controller");
         launch_controller(c, s, from ^ 1);

@@ -75,20 +75,29 @@ struct DevState {
     int64_t ctrl_periods; // decision periods completed (entries pushed to the period ring)
     uint32_t ctrl_on;     // 1: the held proposal is in force
     uint32_t pad2_;
+    double rin[2];        // inlet density minus one used by the step that wrote buffer i
+    uint32_t pend[2];     // 1: the end of the step that wrote buffer i (history record,
+                          // step counter, its inlet sum into s_carry[i]) is still to come
 };
 
 // Inlet density minus one for the step that reads parity rd: the update of
 // eq. potential, rho_in = (rho0 Q* + sum_i K_i) / A in deviation form, moved
 // towards a caller's override or the learned controller's held proposal by
 // at most the bound that comes with it (the plain update judges both).
-__device__ __forceinline__ double inlet_drho_plain(const DevState *st, int rd, double rho0, int64_t a_in)
-{
-    return (rho0 * st->q_target + st->s_carry[rd]) / (double)a_in;
-}
+// DevState as the step kernels read it: through the constant address space,
+// so that every field read is a scalar load. Tile 0 of a step kernel writes
+// a few fields (step_begin), and with a store through the same pointer in the
+// kernel the compiler would read the others -- omega in every tile -- with
+// vector loads, which wait behind the gathers in flight (in FP16 7 % of the
+// step). The fields read this way are not written while the kernel runs.
+typedef const DevState __attribute__((address_space(4))) *CDevState;
+__device__ __forceinline__ CDevState cst(const DevState *p) { return (CDevState)p; }
 
-__device__ __forceinline__ double inlet_drho(const DevState *st, int rd, double rho0, int64_t a_in)
+// carry: the inlet consistency sum sum_i K_i (deviation form).
+template <typename SP>
+__device__ __forceinline__ double inlet_drho_from(SP st, double carry, double rho0, int64_t a_in)
 {
-    const double plain = inlet_drho_plain(st, rd, rho0, a_in);
+    const double plain = (rho0 * st->q_target + carry) / (double)a_in;
     if (st->ovr_on) {
         // a caller's inlet density, judged by the plain update: at most
         // ovr_limit away from it
@@ -103,6 +112,18 @@ __device__ __forceinline__ double inlet_drho(const DevState *st, int rd, double 
     return plain;
 }
 
+// The same from the sum held in s_carry[rd] (valid once the previous step
+// has ended, see step_begin).
+__device__ __forceinline__ double inlet_drho_plain(const DevState *st, int rd, double rho0, int64_t a_in)
+{
+    return (rho0 * st->q_target + st->s_carry[rd]) / (double)a_in;
+}
+
+__device__ __forceinline__ double inlet_drho(const DevState *st, int rd, double rho0, int64_t a_in)
+{
+    return inlet_drho_from(st, st->s_carry[rd], rho0, a_in);
+}
+
 struct StepArgs {
     int64_t n, npad;
     uint32_t f_bytes, nbr_bytes;  // buffer sizes for the descriptors (BUF path)
@@ -115,13 +136,14 @@ struct StepArgs {
     int32_t hist_cap;
     int32_t flux_mode;
     int32_t rd;           // s_carry slot this step reads (its input buffer)
-    int32_t pad_;
+    int32_t part_stride;  // the boundary partials are [2][part_stride]: slot i holds those
+                          // of the step that wrote buffer i
     double rho0, inv_rho0;
     DevState *st;
     const uint64_t *kcoef;          // per site of planes 0-1: 2-bit weight of each post-collision
                                     // population in the next step's inlet sum
-    double *spart;                  // per-tile partial of that sum
-    double *bpart_in, *bpart_out;   // per-tile sums of u_z
+    double *spart;                  // per-tile partial of that sum      [2][part_stride]
+    double *bpart_in, *bpart_out;   // per-tile sums of u_z               [2][part_stride]
     double *obs_mass;               // per-tile sums of rho - 1
     float *obs_umax2;               // per-tile max |u|^2
     uint32_t *obs_bad;              // per-tile non-finite flag
@@ -550,6 +572,7 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
     s = block_sum<BLOCK>(s, lds);
     if (threadIdx.x == 0) {
         a.st->s_carry[a.slot] = s;
+        a.st->pend[a.slot] = 0;  // the next step starts from this sum
         a.st->k_ticket = 0;
     }
 }
@@ -557,11 +580,12 @@ __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin
 // Shared tail of the step kernels (NT threads per tile). OBS: write the
 // tile's watchdog partials (sum of rho - 1, max |u|^2, non-finite flag).
 // Boundary tiles (planes 0-1 and the outlet plane) reduce their u_z sums and
-// their share of the next inlet sum, for k_step_finalize.
+// their share of the next inlet sum into the partials' slot rd ^ 1 (the
+// buffer the step writes), for the end of the step (see step_begin).
 // COLOUR: also the tile's sums of the two colour densities.
 template <int NT, bool OBS, bool COLOUR = false>
 __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_out, double s_next, double m,
-                                              float u2max, uint32_t bad, const StepArgs &a,
+                                              float u2max, uint32_t bad, const StepArgs &a, int rd,
                                               double na_sum = 0.0, double nb_sum = 0.0)
 {
     __shared__ double lds[NT / 64];
@@ -599,63 +623,125 @@ __device__ __forceinline__ void step_epilogue(int tile, double uz_in, double uz_
         }
     }
 
-    // Boundary tiles (planes 0-1 and the outlet plane) write their partial
-    // sums; k_step_finalize reduces them once the step kernel has ended.
     if (!a.flux_mode || !(tile < a.nt01 || tile >= a.tout0)) return;
     const double si = block_sum<NT>(uz_in, lds);
     const double so = block_sum<NT>(uz_out, lds);
     const double sn = block_sum<NT>(s_next, lds);
     if (threadIdx.x == 0) {
-        if (tile < a.nt_in) a.bpart_in[tile] = si;
-        if (tile < a.nt01) a.spart[tile] = sn;
-        if (tile >= a.tout0) a.bpart_out[tile - a.tout0] = so;
+        const int64_t w = (int64_t)(rd ^ 1) * a.part_stride;
+        if (tile < a.nt_in) a.bpart_in[w + tile] = si;
+        if (tile < a.nt01) a.spart[w + tile] = sn;
+        if (tile >= a.tout0) a.bpart_out[w + tile - a.tout0] = so;
     }
 }
 
-// End of a step, launched after the step kernel (one block): the sums of the
-// boundary tiles' partials give Q_in, Q_out and the inlet consistency sum the
-// next step starts from; the step goes into the history and the step counter
-// advances. A launch of its own rather than the last boundary tile to finish
-// (a ticket): the kernel boundary orders every tile's partial before these
-// reads, where the ticket needed a release fence per boundary tile, which
-// writes that XCD's L2 back, and cost about 7 % of the step on a 256^3 pack.
+// End of a step: the sums of its boundary tiles' partials give Q_in, Q_out
+// and the inlet consistency sum the next step starts from; the step goes into
+// the history and the step counter advances. It runs either in a launch of
+// its own after the step kernel (k_step_finalize: the kernel boundary orders
+// every tile's partial before these reads) or, inside a run of steps, in the
+// next step kernel (step_begin), where the inlet tiles also sum the partials
+// themselves instead of waiting for s_carry. Both sum in one fixed order
+// (partials_sum), so a step's results do not depend on which end it had.
+// (The first form was the last boundary tile to finish, found by a ticket:
+// the release fence each boundary tile then needs writes that XCD's L2 back,
+// and cost about 7 % of the step on a 256^3 pack.)
 constexpr int FIN_BLOCK = 256;  // threads of a finalize: the partials in one round of loads
 
+// Sum of n partials in a fixed order for any block of NT >= FIN_BLOCK threads:
+// threads below FIN_BLOCK add every FIN_BLOCK-th entry, the rest add nothing.
+template <int NT>
+__device__ __forceinline__ double partials_sum(const double *p, int n, double *lds)
+{
+    static_assert(NT >= FIN_BLOCK && NT % 64 == 0, "a whole number of waves, at least FIN_BLOCK threads");
+    double v = 0.0;
+    if ((int)threadIdx.x < FIN_BLOCK)
+        for (int i = (int)threadIdx.x; i < n; i += FIN_BLOCK) v += p[i];
+    return block_sum<NT>(v, lds);
+}
+
+// Record the end of the step that wrote buffer w (thread 0 only): ti, to the
+// inlet and outlet u_z sums, tn the next inlet sum.
+__device__ __forceinline__ void end_step_record(const StepArgs &a, int w, double ti, double to, double tn)
+{
+    DevState *st = a.st;
+    const int64_t t = st->step;
+    const double nan = __builtin_nan("");
+    const double r[HIST_STRIDE] = {a.flux_mode ? 1.0 + st->rin[w] : nan, a.flux_mode ? ti : nan,
+                                   a.flux_mode ? to : nan, nan, nan, (double)(t + 1), nan, nan};
+    double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
+    // one 8-byte store each, kept apart by a compiler barrier (see store_pair
+    // in colour.h); plain stores: a volatile one waits for every load in
+    // flight, which inside a step kernel cost the whole step 4 %
+#pragma unroll
+    for (int i = 0; i < HIST_STRIDE; ++i) {
+        h[i] = r[i];
+        __asm__ __volatile__("" ::: "memory");
+    }
+    if (a.flux_mode) st->s_carry[w] = tn;
+    st->step = t + 1;
+}
+
+// Sums of the partials in slot w (the step that wrote buffer w).
+template <int NT>
+__device__ __forceinline__ void end_step_sums(const StepArgs &a, int w, double *lds, double &ti, double &to)
+{
+    const int64_t o = (int64_t)w * a.part_stride;
+    const int nt_out = (int)((a.npad / TILE) - a.tout0);
+    ti = partials_sum<NT>(a.bpart_in + o, a.nt_in, lds);
+    to = partials_sum<NT>(a.bpart_out + o, nt_out, lds);
+}
+
+// The end of the step that read buffer rd, in a launch of its own.
 __device__ __forceinline__ void finalize_step(const StepArgs &a, const int rd)
 {
     __shared__ double lds[FIN_BLOCK / 64];
-    const int nt_in = a.flux_mode ? a.nt_in : 0;
-    const int nt_out = a.flux_mode ? (int)((a.npad / TILE) - a.tout0) : 0;
-    const int nt01 = a.flux_mode ? a.nt01 : 0;
+    const int w = rd ^ 1;
     double ti = 0.0, to = 0.0, tn = 0.0;
-    for (int i = threadIdx.x; i < nt_in; i += FIN_BLOCK) ti += a.bpart_in[i];
-    for (int i = threadIdx.x; i < nt_out; i += FIN_BLOCK) to += a.bpart_out[i];
-    for (int i = threadIdx.x; i < nt01; i += FIN_BLOCK) tn += a.spart[i];
-    ti = block_sum<FIN_BLOCK>(ti, lds);
-    to = block_sum<FIN_BLOCK>(to, lds);
-    tn = block_sum<FIN_BLOCK>(tn, lds);
-    if (threadIdx.x == 0) {
-        DevState *st = a.st;
-        const int64_t t = st->step;
-        // volatile: one 8-byte store each (see store_pair in colour.h)
-        volatile double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
-        if (a.flux_mode) {
-            h[0] = 1.0 + inlet_drho(st, rd, a.rho0, a.a_in);
-            h[1] = ti;
-            h[2] = to;
-            st->s_carry[rd ^ 1] = tn;
-        } else {
-            h[0] = __builtin_nan("");
-            h[1] = __builtin_nan("");
-            h[2] = __builtin_nan("");
-        }
-        h[3] = __builtin_nan("");
-        h[4] = __builtin_nan("");
-        h[5] = (double)(t + 1);
-        h[6] = __builtin_nan("");
-        h[7] = __builtin_nan("");
-        st->step = t + 1;
+    if (a.flux_mode) {
+        end_step_sums<FIN_BLOCK>(a, w, lds, ti, to);
+        tn = partials_sum<FIN_BLOCK>(a.spart + (int64_t)w * a.part_stride, a.nt01, lds);
     }
+    if (threadIdx.x == 0) {
+        end_step_record(a, w, ti, to, tn);
+        a.st->pend[w] = 0;
+    }
+}
+
+// Start of a step that reads buffer rd, for the tile `tile` (block-uniform;
+// every thread of the tile calls it). Returns the inlet density minus one on
+// the inlet tiles (0 elsewhere). When the step that wrote buffer rd has not
+// ended yet (pend[rd]: runs of steps launch no k_step_finalize in between),
+// the inlet tiles sum its partials themselves and tile 0 records its end. Tile
+// 0 then marks this step's end as pending, with its inlet density for the
+// record. pend[rd] and s_carry[rd] are not written by this kernel while it
+// reads them (tile 0 writes s_carry[rd] only when pend[rd] is set, and then
+// nobody reads it).
+template <int NT>
+__device__ __forceinline__ double step_begin(int tile, const StepArgs &a, int rd)
+{
+    __shared__ double lds[NT / 64];
+    const bool inlet = a.flux_mode && tile < a.nt_in;
+    if (!inlet && tile != 0) return 0.0;
+    DevState *st = a.st;
+    const bool pend = cst(st)->pend[rd] != 0;
+    double drho = 0.0, carry = 0.0;
+    if (inlet) {
+        carry = pend ? partials_sum<NT>(a.spart + (int64_t)rd * a.part_stride, a.nt01, lds) : cst(st)->s_carry[rd];
+        drho = inlet_drho_from(cst(st), carry, a.rho0, a.a_in);
+    }
+    if (tile == 0) {
+        if (pend) {
+            double ti = 0.0, to = 0.0;
+            if (a.flux_mode) end_step_sums<NT>(a, rd, lds, ti, to);
+            if (threadIdx.x == 0) end_step_record(a, rd, ti, to, carry);
+        }
+        if (threadIdx.x == 0) {
+            st->rin[rd ^ 1] = drho;
+            st->pend[rd ^ 1] = 1;
+        }
+    }
+    return drho;
 }
 
 __global__ __launch_bounds__(FIN_BLOCK) void k_step_finalize(StepArgs a)
@@ -941,9 +1027,11 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         }
     }
 
+    // after the gathers are issued: the inlet tiles' sums and tile 0's
+    // record then wait with them, and every other tile starts as before
+    const double drho_in = step_begin<SC_BLOCK>(tile, a, rd);
     double uz_in = 0.0, uz_out = 0.0;
     if (tile < a.nt_in) {
-        const double drho_in = inlet_drho(a.st, rd, a.rho0, a.a_in);
 #pragma unroll
         for (int v = 0; v < V; ++v)
             if (s0 + v < a.a_in) {
@@ -957,12 +1045,12 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         for (int v = 0; v < V; ++v)
             if (s0 + v >= a.out0 && s0 + v < a.n) {
                 rescale_pops<T, SCALED, false>(g[v]);
-                uz_out += outlet_condition(g[v], a.st->drho_out, a.rho0);
+                uz_out += outlet_condition(g[v], cst(a.st)->drho_out, a.rho0);
                 rescale_pops<T, SCALED, true>(g[v]);
             }
     }
 
-    const R omega = (R)a.st->omega;
+    const R omega = (R)cst(a.st)->omega;
     double m = 0.0;
     float u2max = 0.f;
     uint32_t bad = 0;
@@ -1026,7 +1114,7 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         }
     }
 
-    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a);
+    step_epilogue<SC_BLOCK, OBS>(tile, uz_in, uz_out, s_next, m, u2max, bad, a, rd);
 }
 
 template <typename T, bool OBS, bool BUF, bool MRT = false>
@@ -1036,6 +1124,18 @@ __global__ __launch_bounds__(SC_BLOCK) void k_stream_collide(const T *__restrict
                                                              StepArgs a)
 {
     stream_collide_tile<T, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a, a.rd);
+}
+
+// The FP16 step, held to 80 scalar registers: it waits on latency, and the
+// inlet tiles' sums and tile 0's record of the previous step (step_begin)
+// took it from 78 to 83 scalar registers and its step from 130 to 134 us on
+// a 256^3 pack; at 80 (the few values beyond go to VGPR lanes) it takes
+// 131 us. The FP32 step gains nothing from such a bound.
+template <bool OBS, bool BUF, bool MRT = false>
+__global__ __launch_bounds__(SC_BLOCK) __attribute__((amdgpu_num_sgpr(80))) void k_stream_collide_h(
+    const _Float16 *__restrict__ fin, _Float16 *__restrict__ fout, const int32_t *__restrict__ nbr, StepArgs a)
+{
+    stream_collide_tile<_Float16, OBS, BUF, MRT>((int)blockIdx.x, fin, fout, nbr, a, a.rd);
 }
 
 // Batched step: many lattices in one launch. Each lattice keeps its own
