@@ -157,7 +157,11 @@ flbm_status flbm_set_target_flux(flbm_ctx *c, double q_target);
 /* Outlet density used from the next step on. */
 flbm_status flbm_set_outlet_density(flbm_ctx *c, double rho_out);
 
-/* Enqueue n time steps on the context's stream (asynchronous). */
+/* Enqueue n time steps on the context's stream (asynchronous). Within the n
+ * steps each step kernel also ends the step before it (history record,
+ * carried inlet sum); the last one ends in a launch of its own (every step
+ * does, for the colour model and under the learned controller), so once the
+ * stream has reached the end of the call every step is recorded. */
 flbm_status flbm_step(flbm_ctx *c, int32_t n);
 
 /* Wait for the context's stream. Returns FLBM_EUNSTABLE if a watchdog check
