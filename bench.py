@@ -40,7 +40,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in ("kernels.h", "engine.hip", "pull_format.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", f) for f in ("kernels.h", "engine.hip", "pull_format.h")] + [
+    os.path.join(ROOT, "paper_1806_10589_amd", "build.py")]  # its compile flags shape the kernels too
 COLOUR_SOURCES = KERNEL_SOURCES + [os.path.join(ROOT, "paper_1806_10589_amd", "csrc", "colour.h")]
 
 # Two-fluid pack workload: interfacial tension gamma = 0.01, reached at

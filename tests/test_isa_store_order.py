@@ -17,6 +17,8 @@ import subprocess
 
 import pytest
 
+from paper_1806_10589_amd import build
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1806_10589_amd", "csrc")
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -27,9 +29,9 @@ pytestmark = pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not ava
 
 def _assembly(src, tmp_path):
     out = tmp_path / (os.path.basename(src) + ".s")
-    cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"), "-S",
-           "--offload-device-only", src, "-o", str(out)]
+    # the library's own flags, less linking
+    flags = [f for f in build.HIPCC_FLAGS if f not in ("-shared", "-Wall")]
+    cmd = [HIPCC] + flags + ["-S", "--offload-device-only", src, "-o", str(out)]
     subprocess.run(cmd, check=True, capture_output=True, timeout=600)
     return out.read_text().splitlines()
 
