@@ -1,13 +1,14 @@
 // C-ABI of the library: context, device memory, step orchestration, the
 // learned inlet controller and batched stepping.
 //
-// One single-fluid step is two launches on the caller's stream (Methods, the
+// One single-fluid step is one launch on the caller's stream (Methods, the
 // paragraph after eq. potential: the inlet density is found from the
 // streamed knowns, then the pressure condition is applied, then collision):
 // k_stream_collide pulls, applies the boundary conditions with the inlet
 // density of eq. potential, collides (BGK or MRT), stores, and writes per-tile
 // partials of Q_in, Q_out and of the inlet sum that the next step's inlet
-// sites will pull; k_step_finalize (one block) reduces them. With pull streaming
+// sites will pull; the next step kernel reduces them (step_begin), and after
+// the last step of a run k_step_finalize (one block) does. With pull streaming
 // the "streamed" values of a step are gathers of the stored state, so no
 // grid-wide barrier is needed inside a step; k_inlet_plane computes the sum
 // from the state only after the host has written it. The colour model adds

@@ -537,8 +537,9 @@ __device__ __forceinline__ void bgk_collide(R (&g)[19], R omega, R rho0, R inv_r
 // sums the consistency sums of its inlet sites from the pulled values; blocks
 // write FP64 partials; the last block to finish sums them in block order into
 // s_carry[slot]. The fused step kernel turns it into rho_in, and each step's
-// finalize hands the sum of the following step over, so this kernel runs only
-// when a run of steps starts from a state the step kernels did not produce.
+// end (step_begin, finalize_step) hands the sum of the following step over, so
+// this kernel runs only when a run of steps starts from a state the step
+// kernels did not produce.
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void k_inlet_plane(const T *__restrict__ fin,
                                                        const int32_t *__restrict__ nbr,
@@ -753,7 +754,8 @@ __global__ __launch_bounds__(FIN_BLOCK) void k_step_finalize(StepArgs a)
 // outlet pressure condition where the site lies on z = 0 or z = nz-1, BGK
 // collide, store. Each thread owns SC_V consecutive sites. Tiles holding
 // boundary sites also reduce sum u_z (FP64) and their share of the next inlet
-// sum, which k_step_finalize turns into Q_in, Q_out and the next step's start.
+// sum, which the step's end (step_begin of the next step kernel, or
+// k_step_finalize) turns into Q_in, Q_out and the next step's start.
 // OBS: also write per-tile partials of mass, max |u|^2 and a non-finite flag.
 // Mass-exact store of a collided site in reduced precision: the rest
 // population takes the site's pre-collision mass minus what the other 18
