@@ -88,7 +88,7 @@ struct DevState {
 // so that every field read is a scalar load. Tile 0 of a step kernel writes
 // a few fields (step_begin), and with a store through the same pointer in the
 // kernel the compiler would read the others -- omega in every tile -- with
-// vector loads, which wait behind the gathers in flight (in FP16 7 % of the
+// vector loads, which wait behind the gathers in flight (3-4 % of the FP16
 // step). The fields read this way are not written while the kernel runs.
 typedef const DevState __attribute__((address_space(4))) *CDevState;
 __device__ __forceinline__ CDevState cst(const DevState *p) { return (CDevState)p; }
@@ -672,8 +672,9 @@ __device__ __forceinline__ void end_step_record(const StepArgs &a, int w, double
                                    a.flux_mode ? to : nan, nan, nan, (double)(t + 1), nan, nan};
     double *h = a.hist + (t % a.hist_cap) * HIST_STRIDE;
     // one 8-byte store each, kept apart by a compiler barrier (see store_pair
-    // in colour.h); plain stores: a volatile one waits for every load in
-    // flight, which inside a step kernel cost the whole step 4 %
+    // in colour.h); plain stores, since a volatile one is followed by a wait
+    // for every memory operation of the wave in flight (in a step kernel, the
+    // tile's gathers)
 #pragma unroll
     for (int i = 0; i < HIST_STRIDE; ++i) {
         h[i] = r[i];
