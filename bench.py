@@ -86,7 +86,7 @@ def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share
     512 sites; of the 8-bit tiles, the share share_run that the step reads as
     run codes takes 8 bytes per site instead of 18, and 4 more on the share
     share_wide of waves (of all waves) whose list of codes needs a second
-    word (not in FP16 storage, whose steps read the 8-bit codes).
+    word (not in the colour model's FP16 step, which reads the 8-bit codes).
     The colour model adds, per site: in the phase pass the 7
     colour pairs (A_q, B_q) read (6 of them pulled, with the codes of
     directions 1-6: 2 words of byte codes, 3 of 16-bit codes or 6 int32) and
@@ -95,7 +95,7 @@ def bytes_per_lup(precision: str, model: str = "bgk", share8: float = 0.0, share
     colours are FP64 in FP64 storage and FP32 otherwise."""
     elem = {"fp64": 8, "fp32": 4, "fp16dev": 2}[precision]
     hdr = 80 / 512
-    if precision == "fp16dev":
+    if precision == "fp16dev" and model == "colour":
         share_run = share_wide = 0.0
     table = (18 * 4 * (1.0 - share8 - share16) + (18 + hdr) * (share8 - share_run) + (8 + hdr) * share_run
              + 4 * share_wide + (36 + hdr) * share16)

@@ -400,10 +400,11 @@ flbm_status flbm_get_pull_table(const flbm_ctx *c, int32_t *nbr);
  *                      directions whose code differs from the previous
  *                      site's and the wave's list of those codes (at most
  *                      512): 8 bytes per site, 12 where a wave lists more
- *                      than 256 codes. Not in FP16 storage, whose steps
- *                      read the 8-bit codes (decoding runs costs them more
- *                      than the bytes saved). COMPACT and RUN share one
- *                      table, so switching between them rebuilds nothing.
+ *                      than 256 codes. Not in the colour model's FP16
+ *                      step, which reads the 8-bit codes (decoding runs
+ *                      costs it more than the bytes saved). COMPACT and RUN
+ *                      share one table, so switching between them rebuilds
+ *                      nothing.
  * A tile whose sources of some direction span more than a form's range
  * falls back to the next wider form, down to the int32 table. Both passes of
  * the colour model read it too (the phase pass directions 1..6). Lattices

@@ -695,9 +695,9 @@ __global__ __launch_bounds__(TILE, sizeof(T) <= 4 ? COLOUR_WAVES : 1) void k_col
             if (d3q19::cz[q]) gz -= d3q19::cz[q] * w3 * ph;
         }
     };
-    // run codes where the table has them, except in FP16 storage (the same
-    // rule and reason as the single-fluid step: 2 % off the FP32 colour
-    // step, 3 % onto the FP16 one)
+    // run codes where the table has them, except in FP16 storage: 2 % off
+    // the FP32 colour step, 1-3 % onto the FP16 one (whose decode lengthens a
+    // latency chain the single-fluid FP16 step has shortened enough to gain)
     if (form == PULL_TILE_BYTE && !std::is_same<T, _Float16>::value && a.pull_runs && hdr_entry(hdr, PULL_HDR_RUNS))
         gather(std::integral_constant<int, FORM_RUN>{});
     else if (form == PULL_TILE_BYTE)

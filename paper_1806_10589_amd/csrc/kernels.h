@@ -928,12 +928,13 @@ __device__ __forceinline__ void stream_collide_tile(const int tile, const T *__r
         // 6 % off the FP16 step, which waits on latency, and 1 % onto the
         // FP32 step and the colour passes, which wait on bandwidth
         constexpr bool SPEC = std::is_same<T, _Float16>::value;
-        // run codes: one site per lane, where the table carries them, and not
-        // in FP16, whose step waits on latency: decoding them (a ballot, a
-        // lane count and a cross-lane read per direction) made it 3 % slower,
-        // while the 10 bytes per site they save take 4 % off the FP32 step,
-        // which waits on bandwidth
-        const bool runs_on = V == 1 && !SPEC && a.pull_runs != nullptr;
+        // run codes: one site per lane, where the table carries them. The 10
+        // bytes per site they save take 4 % off the FP32 step, which waits on
+        // bandwidth, and 3 % off the FP16 step, whose latency chain their
+        // decode (a ballot, a lane count and a cross-lane read per direction)
+        // lengthens: that made it 3 % slower as long as its last gather
+        // waited for all the others (see build.py)
+        const bool runs_on = V == 1 && a.pull_runs != nullptr;
         const __amdgpu_buffer_rsrc_t rr = make_rsrc(a.pull_runs, a.runs_bytes);
         uint32_t w[4][V];
         uint16_t tl[V];
