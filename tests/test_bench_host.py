@@ -26,6 +26,14 @@ def test_design_byte_counts():
     assert abs(bench.bytes_per_lup("fp32", "bgk", 1.0, 0.0) - (152 + 18 + 80 / 512)) < 1e-12
     # colour, int32 table: f 152 + 72; phase pass 56 + 24 + 8; colour step 8 + 56
     assert bench.bytes_per_lup("fp32", "colour") == 224 + 88 + 64
+    # run codes: 8 bytes per site where the 8-bit codes take 18, 4 more on
+    # wide waves; the single-fluid FP16 step reads them, the FP16 colour step
+    # the 8-bit codes
+    hdr = 80 / 512
+    assert abs(bench.bytes_per_lup("fp16dev", "bgk", 1.0, 0.0, 1.0, 0.5) - (76 + 8 + hdr + 2)) < 1e-12
+    assert abs(bench.bytes_per_lup("fp32", "bgk", 1.0, 0.0, 0.5, 0.0) - (152 + 13 + hdr)) < 1e-12
+    assert bench.bytes_per_lup("fp16dev", "colour", 1.0, 0.0, 1.0, 0.5) == bench.bytes_per_lup(
+        "fp16dev", "colour", 1.0, 0.0)
 
 
 def test_two_fluid_workload_uses_the_oracle_calibration():
